@@ -1,0 +1,157 @@
+"""ctypes binding of the C oracle (test infrastructure only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "minsum_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+_u8p = ctypes.POINTER(ctypes.c_uint8)
+_f32p = ctypes.POINTER(ctypes.c_float)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_i32 = ctypes.c_int32
+
+
+def build_oracle(mutant: int = 0, out: str | None = None) -> str:
+    """Compile the oracle (or a variant with a planted mistake) and return
+    the path of the shared library."""
+    out = out or (LIB if mutant == 0 else os.path.join(HERE, f"liboracle_mutant{mutant}.so"))
+    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+           f"-DORACLE_MUTANT={mutant}", SRC, "-o", out + ".tmp", "-lpthread", "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(out + ".tmp", out)
+    return out
+
+
+def _p(a, t):
+    return None if a is None else a.ctypes.data_as(t)
+
+
+class Oracle:
+    def __init__(self, path: str):
+        lib = ctypes.CDLL(path)
+        lib.oracle_minsum_decode.argtypes = [_u8p, _i32, _i32, _f32p, _i32, _i32, _i32, _u8p, _f32p,
+                                             _i32p, _u8p, _i32]
+        lib.oracle_minsum_decode.restype = ctypes.c_int
+        lib.oracle_nms_decode.argtypes = [_u8p, _i32, _i32, _f32p, _i32, _i32, _i32, _f32p, _f32p, _i32,
+                                          _i32, _u8p, _f32p, _i32p, _u8p, _i32]
+        lib.oracle_nms_decode.restype = ctypes.c_int
+        lib.oracle_minsum_dense.argtypes = [_u8p, _i32, _i32, _f32p, _i32, _i32, _u8p, _f32p, _i32p, _u8p]
+        lib.oracle_minsum_dense.restype = ctypes.c_int
+        lib.oracle_syndrome.argtypes = [_u8p, _i32, _i32, _u8p, _i32, _u8p]
+        lib.oracle_syndrome.restype = ctypes.c_int
+        lib.oracle_check_degrees.argtypes = [_u8p, _i32, _i32, _i32p, _i32]
+        lib.oracle_check_degrees.restype = _i32
+        self.lib = lib
+        self.path = path
+
+    def minsum_decode(self, H, llr, max_iter, early_exit=True, nthreads=0):
+        """Algorithm 1 on every frame of ``llr`` (B, n).  Returns
+        (bits uint8 (B,n), post float32 (B,n), iters int32 (B,), ok uint8 (B,))."""
+        H = np.ascontiguousarray(H, dtype=np.uint8)
+        llr = np.ascontiguousarray(llr, dtype=np.float32)
+        m, n = H.shape
+        B = llr.shape[0]
+        assert llr.shape == (B, n)
+        bits = np.empty((B, n), np.uint8)
+        post = np.empty((B, n), np.float32)
+        iters = np.empty(B, np.int32)
+        ok = np.empty(B, np.uint8)
+        st = self.lib.oracle_minsum_decode(_p(H, _u8p), m, n, _p(llr, _f32p), B, int(max_iter),
+                                           int(bool(early_exit)), _p(bits, _u8p), _p(post, _f32p),
+                                           _p(iters, _i32p), _p(ok, _u8p), int(nthreads))
+        if st:
+            raise ValueError(f"oracle_minsum_decode status {st}")
+        return bits, post, iters, ok
+
+    def nms_decode(self, H, llr, max_iter, alpha, beta, early_exit=True, nthreads=0):
+        H = np.ascontiguousarray(H, dtype=np.uint8)
+        llr = np.ascontiguousarray(llr, dtype=np.float32)
+        alpha = np.ascontiguousarray(alpha, dtype=np.float32)
+        beta = np.ascontiguousarray(beta, dtype=np.float32)
+        T, C = alpha.shape
+        assert beta.shape == (T, C)
+        m, n = H.shape
+        B = llr.shape[0]
+        bits = np.empty((B, n), np.uint8)
+        post = np.empty((B, n), np.float32)
+        iters = np.empty(B, np.int32)
+        ok = np.empty(B, np.uint8)
+        st = self.lib.oracle_nms_decode(_p(H, _u8p), m, n, _p(llr, _f32p), B, int(max_iter),
+                                        int(bool(early_exit)), _p(alpha, _f32p), _p(beta, _f32p), T, C,
+                                        _p(bits, _u8p), _p(post, _f32p), _p(iters, _i32p), _p(ok, _u8p),
+                                        int(nthreads))
+        if st:
+            raise ValueError(f"oracle_nms_decode status {st}")
+        return bits, post, iters, ok
+
+    def minsum_dense(self, H, r, max_iter, early_exit=True):
+        """Algorithm 2 on one frame r (n,)."""
+        H = np.ascontiguousarray(H, dtype=np.uint8)
+        r = np.ascontiguousarray(r, dtype=np.float32)
+        m, n = H.shape
+        bits = np.empty(n, np.uint8)
+        post = np.empty(n, np.float32)
+        it = np.empty(1, np.int32)
+        ok = np.empty(1, np.uint8)
+        st = self.lib.oracle_minsum_dense(_p(H, _u8p), m, n, _p(r, _f32p), int(max_iter), int(bool(early_exit)),
+                                          _p(bits, _u8p), _p(post, _f32p), _p(it, _i32p), _p(ok, _u8p))
+        if st:
+            raise ValueError(f"oracle_minsum_dense status {st}")
+        return bits, post, int(it[0]), int(ok[0])
+
+    def syndrome(self, H, bits):
+        H = np.ascontiguousarray(H, dtype=np.uint8)
+        bits = np.ascontiguousarray(np.atleast_2d(bits), dtype=np.uint8)
+        m, n = H.shape
+        out = np.empty((bits.shape[0], m), np.uint8)
+        st = self.lib.oracle_syndrome(_p(H, _u8p), m, n, _p(bits, _u8p), bits.shape[0], _p(out, _u8p))
+        if st:
+            raise ValueError("oracle_syndrome failed")
+        return out
+
+    def check_degrees(self, H):
+        H = np.ascontiguousarray(H, dtype=np.uint8)
+        m, n = H.shape
+        deg = np.zeros(n + 1, np.int32)
+        c = self.lib.oracle_check_degrees(_p(H, _u8p), m, n, _p(deg, _i32p), n + 1)
+        if c < 0:
+            raise ValueError(f"oracle_check_degrees status {c}")
+        return deg[:c].copy()
+
+
+_default: Oracle | None = None
+
+
+def load_oracle() -> Oracle:
+    global _default
+    if _default is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            build_oracle()
+        _default = Oracle(LIB)
+    return _default
+
+
+def minsum_decode(*a, **k):
+    return load_oracle().minsum_decode(*a, **k)
+
+
+def nms_decode(*a, **k):
+    return load_oracle().nms_decode(*a, **k)
+
+
+def minsum_dense(*a, **k):
+    return load_oracle().minsum_dense(*a, **k)
+
+
+def syndrome(*a, **k):
+    return load_oracle().syndrome(*a, **k)
+
+
+def check_degrees(*a, **k):
+    return load_oracle().check_degrees(*a, **k)
