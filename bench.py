@@ -1,0 +1,215 @@
+#!/usr/bin/env python
+"""Throughput of batched Min-Sum LDPC decoding on one MI355X.
+
+Workload (default): the (3,6)-regular code n = 1024, m = 512 (seeded
+edge-socket construction), 65,536 random codewords per Eb/N0 point, BPSK over
+AWGN at Eb/N0 = 1.0, 1.5, ..., 4.0 dB (7 points), at most 50 iterations with
+per-frame syndrome exit.  One step decodes all 7 batches (458,752 frames);
+inputs are generated on the GPU and resident in HBM before timing starts.
+
+Prints one JSON line: coded Gbit/s (value), edge-messages/s, the roofline of
+the dominant kernel (algorithmic bytes over its event-timed duration), and the
+CPU oracle timed on a bounded sample of the same frames.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, AMD published
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="regular1024", choices=["regular1024", "qc64800", "regular96"])
+    ap.add_argument("--path", default="auto", choices=["auto", "stream", "onchip"])
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-only", action="store_true", help="warmup + timed steps, no extras (for rocprofv3)")
+    return ap.parse_args()
+
+
+def workload(name):
+    from paper_2507_10424_amd import workloads as wl
+    if name == "regular1024":
+        H = wl.regular_ldpc(1024, 512, 3, 6, seed=2)
+        return dict(name="(3,6)-regular n=1024 m=512, 65536 random codewords x 7 Eb/N0 points 1.0..4.0 dB, "
+                         "L=50, early exit", H=H, batch=65536, ebn0=[1.0, 1.5, 2.0, 2.5, 3.0, 3.5, 4.0],
+                    L=50, rate=0.5, random_cw=True, seed_cw=200, seed_noise=300)
+    if name == "qc64800":
+        H = wl.large_qc_code(seed=5)
+        return dict(name="irregular QC n=64800 m=32400 Z=360, 4096 all-zero frames x Eb/N0 1.0..1.6 dB, L=50, "
+                         "early exit", H=H, batch=4096, ebn0=[1.0, 1.2, 1.4, 1.6], L=50, rate=0.5,
+                    random_cw=False, seed_cw=0, seed_noise=500)
+    H = wl.regular_ldpc(96, 48, 3, 6, seed=1)
+    return dict(name="(3,6)-regular n=96 m=48, 1000 all-zero frames at 2 dB, L=20", H=H, batch=1000, ebn0=[2.0],
+                L=20, rate=0.5, random_cw=False, seed_cw=0, seed_noise=100)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the decoder shards frames across GPUs "
+              "by running one independent process per GPU, which this build does not launch", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2507_10424_amd import ldpc
+    from paper_2507_10424_amd import workloads as wl
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    lib = ldpc.load_library()
+    import ctypes
+    lib.ldpc_timing_enable.argtypes = [ctypes.c_int]
+    lib.ldpc_timing_read.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_int64)]
+
+    W = workload(args.config)
+    H = W["H"]
+    m, n = H.shape
+    B, L = W["batch"], W["L"]
+    flags = {"auto": 0, "stream": ldpc.LDPC_FORCE_STREAM, "onchip": ldpc.LDPC_FORCE_ONCHIP}[args.path]
+    log(f"[bench] workload: {W['name']}")
+    t0 = time.time()
+    g = ldpc.build_graph(torch.from_numpy(H).to(dev))
+    E = g.E
+    enc = wl.gf2_encoder(H) if W["random_cw"] else None
+    llrs, cws = [], []
+    for p, eb in enumerate(W["ebn0"]):
+        if enc is not None:
+            cw = enc.random_codewords_torch(B, W["seed_cw"] + p, dev)
+        else:
+            cw = None
+        llrs.append(wl.bpsk_awgn_llr_torch(cw, eb, W["rate"], W["seed_noise"] + p, dev, n=n, batch=B))
+        cws.append(cw)
+    torch.cuda.synchronize()
+    log(f"[bench] inputs ready on the GPU in {time.time() - t0:.1f} s ({len(llrs)} x {B} x {n})")
+
+    ws = torch.empty(max(1, ldpc.workspace_bytes(g, B, flags)), dtype=torch.uint8, device=dev)
+    outs = [ldpc._outputs(B, n, dev, True) for _ in llrs]
+
+    def step():
+        for x, o in zip(llrs, outs):
+            ldpc.minsum_decode(g, x, L, flags=flags, workspace=ws, out=o)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for _ in range(args.steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    ms_total = ev0.elapsed_time(ev1)
+    ms_step = ms_total / args.steps
+    frames_step = B * len(llrs)
+    gbits = frames_step * n / (ms_step * 1e-3) / 1e9
+    log(f"[bench] {args.steps} steps, {ms_step:.3f} ms/step, {gbits:.2f} coded Gbit/s")
+    if args.profile_only:
+        print(json.dumps({"ms_per_step": ms_step, "value": gbits}))
+        return
+
+    # decoding statistics of the last step
+    iters_all = [o[2].to(torch.int64) for o in outs]
+    tot_iters = int(sum(int(i.sum()) for i in iters_all))
+    per_point = []
+    for p, (eb, o) in enumerate(zip(W["ebn0"], outs)):
+        bits, _, it, ok = o
+        ref = cws[p] if cws[p] is not None else torch.zeros_like(bits)
+        err = (bits != ref)
+        fe = int(err.any(dim=1).sum())
+        per_point.append(dict(ebn0_db=eb, mean_iters=round(float(it.float().mean()), 3), fer=fe / B,
+                              ber=float(err.sum()) / (B * n), converged=float(ok.float().mean())))
+    edge_msgs = 2.0 * E * tot_iters / (ms_step * 1e-3)
+    k_info = (n - wl.gf2_encoder(H).rank) if W["random_cw"] else None
+
+    # per-kernel durations from HIP events on the decode stream (one more step)
+    lib.ldpc_timing_enable(1)
+    step()
+    torch.cuda.synchronize()
+    ktimes = {}
+    for kid, kname in [(0, "check"), (1, "bit"), (2, "onchip")]:
+        ms, cnt = ctypes.c_double(), ctypes.c_int64()
+        lib.ldpc_timing_read(kid, ctypes.byref(ms), ctypes.byref(cnt))
+        if cnt.value:
+            ktimes[kname] = (ms.value, cnt.value)
+    lib.ldpc_timing_enable(0)
+    dom = max(ktimes, key=lambda k: ktimes[k][0])
+    dom_ms, dom_launches = ktimes[dom]
+    # algorithmic HBM bytes of that kernel over the step (per frame-iteration:
+    # check 8E + 4n (4E + 4n in iteration 1, which reads no messages),
+    # bit 4E + 8n; the on-chip kernel moves only frame I/O: 4n in, 5n + 5 out)
+    its = torch.cat(iters_all).to(torch.float64)
+    if dom == "check":
+        algo = float(((its >= 1).double() * (4 * E + 4 * n) + (its - 1).clamp(min=0) * (8 * E + 4 * n)).sum())
+    elif dom == "bit":
+        algo = float((its * (4 * E + 8 * n)).sum())
+    else:
+        algo = float(frames_step * (9 * n + 5))
+    achieved = algo / (dom_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                "kernel_ms_per_launch": round(dom_ms / dom_launches, 4), "launches_per_step": dom_launches}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        per = max(1, int(2 * 1024 / max(len(llrs), 1)))
+        # size the sample to about --cpu-seconds: probe with a few frames first
+        probe = [x[:8].cpu().numpy() for x in llrs]
+        nthreads = os.cpu_count() or 1
+        nthreads = min(nthreads, 16)
+        tp = time.time()
+        for x in probe:
+            oracle.minsum_decode(H, x, L, nthreads=1)
+        t_probe = (time.time() - tp) / (8 * len(probe))  # s per frame on one core
+        per = max(4, min(B, int(args.cpu_seconds * nthreads / max(t_probe, 1e-6) / len(llrs))))
+        sample = [x[:per].cpu().numpy() for x in llrs]
+        tc = time.time()
+        ref = [oracle.minsum_decode(H, x, L, nthreads=nthreads) for x in sample]
+        t_cpu = time.time() - tc
+        cpu_frames = per * len(sample)
+        cpu = {"value": round(cpu_frames * n / t_cpu / 1e9, 6), "unit": "Gbit/s", "cores": nthreads,
+               "kind": "oracle", "sample": f"first {per} frames of each of the {len(sample)} Eb/N0 batches "
+                                           f"({cpu_frames} frames, {t_cpu:.1f} s)"}
+        # parity of the timed GPU outputs on the sample
+        mism = 0
+        for (ob, op, oi, oo), o in zip(ref, outs):
+            gb = o[0][:per].cpu().numpy()
+            gi = o[2][:per].cpu().numpy()
+            mism += int(np.any(gb != ob, axis=1).sum()) + int((gi != oi).sum())
+        cpu["gpu_mismatches_on_sample"] = mism
+
+    line = {
+        "metric": "coded Gbit/s & edge-msg/s (% HBM BW); neural vs plain Min-Sum at equal FER",
+        "value": round(gbits, 3), "unit": "Gbit/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": W["name"], "n": n, "m": m, "edges": E, "batch": B, "batches_per_step": len(llrs),
+                   "ebn0_db": W["ebn0"], "max_iter": L, "path": args.path},
+        "edge_msg_per_s": edge_msgs, "info_gbit_s": round(gbits * k_info / n, 3) if k_info else None,
+        "mean_iters": round(tot_iters / frames_step, 3), "per_point": per_point,
+        "roofline": roofline, "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

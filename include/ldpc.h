@@ -1,0 +1,170 @@
+/*
+ * libldpc: batched Min-Sum LDPC decoding on AMD Instinct MI355X (gfx950).
+ *
+ * Method: "A mapping of the Min-Sum decoder to reduction operations, and its
+ * implementation using CUDA kernels" (Sella & Heinis).  The parity matrix H is
+ * a run-time argument; only its dimensions are fixed when a graph is built.
+ *
+ * Conventions shared by every entry point
+ *   - Pointers named *_dev are device memory on the current HIP device; the
+ *     caller allocates and owns them.  The library owns only the arrays inside
+ *     an ldpc_graph (allocated by ldpc_build_graph, freed by
+ *     ldpc_graph_destroy).
+ *   - Matrices are dense and row-major: H is m x n, per-frame arrays are
+ *     B x n with frame b's n values contiguous.
+ *   - LLR polarity: a positive LLR favours bit 0.  Hard decision: bit = 1 iff
+ *     the posterior is < 0 (so a posterior of +-0 decides 0).
+ *   - Decoding calls are asynchronous on `stream`, allocate nothing, never
+ *     synchronise the host and do not read anything back; they can be
+ *     captured into a HIP graph.  Argument errors are reported before
+ *     anything is launched; launch failures are reported as LDPC_EHIP.
+ *   - Every entry point returns an LDPC_* status (0 = success) unless noted.
+ */
+#ifndef LDPC_H
+#define LDPC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ldpc_graph ldpc_graph; /* opaque; immutable once built */
+
+enum ldpc_status {
+    LDPC_OK = 0,
+    LDPC_EINVAL = -1,      /* bad argument: null pointer, negative size, ... */
+    LDPC_EBADH = -2,       /* H holds a value other than 0/1, or a row of degree 1 */
+    LDPC_ENOMEM = -3,      /* device or host allocation failed (graph build only) */
+    LDPC_EHIP = -4,        /* a HIP call or kernel launch failed */
+    LDPC_EWORKSPACE = -5,  /* workspace null or smaller than required */
+    LDPC_EUNSUPPORTED = -6 /* the graph exceeds a limit of the requested kernel path */
+};
+
+/* Decode flags (bitwise OR). */
+enum ldpc_flags {
+    /* Run exactly max_iter iterations for every frame (no syndrome exit). */
+    LDPC_NO_EARLY_EXIT = 1u << 0,
+    /* Force the HBM-streaming kernels (state in device memory, one launch per
+     * half-iteration) even where the graph fits the on-chip path. */
+    LDPC_FORCE_STREAM = 1u << 1,
+    /* Force the on-chip kernel (one workgroup per frame group, state in LDS);
+     * LDPC_EUNSUPPORTED if the graph does not fit. */
+    LDPC_FORCE_ONCHIP = 1u << 2
+};
+
+/*
+ * Build the Tanner graph of H (Sec. II-B: the neighbour sets N_i of each check
+ * row and M_j of each bit column) on the device.
+ *   H_dev   m x n uint8 row-major, entries 0 or 1.  Read only; may be freed
+ *           after the call returns.
+ *   m, n    numbers of checks and bits, m >= 1, n >= 1, number of ones < 2^31.
+ *   stream  stream for the build kernels; the call synchronises it before it
+ *           returns (it reads degree counts back), so it must not be captured.
+ *   out     receives the graph.  On failure *out is set to NULL.
+ * Edges are numbered row by row with ascending bit index inside a row; each
+ * bit's checks are kept in ascending check index, which fixes the order of
+ * the bit-node sum.  Check rows are grouped by degree into classes (rank of
+ * the degree among the distinct nonzero row degrees, ascending), used by the
+ * learned decoder's per-degree weights.
+ * Errors: LDPC_EINVAL (null pointer, m or n < 1), LDPC_EBADH (entry not 0/1,
+ * or a row with exactly one 1, whose Min-Sum message is undefined; also more
+ * than 2^31 - 1 ones), LDPC_ENOMEM, LDPC_EHIP.
+ */
+int ldpc_build_graph(const uint8_t *H_dev, int32_t m, int32_t n, hipStream_t stream,
+                     ldpc_graph **out);
+
+/*
+ * Graph facts.  Any output pointer may be NULL.  check_degrees (host memory,
+ * `cap` entries) receives the distinct nonzero row degrees in ascending order;
+ * n_classes receives their count.
+ */
+int ldpc_graph_info(const ldpc_graph *g, int32_t *m, int32_t *n, int64_t *n_edges,
+                    int32_t *dc_max, int32_t *dv_max, int32_t *n_classes,
+                    int32_t *check_degrees, int32_t cap);
+
+/* Free a graph (NULL is allowed).  Synchronises the device first. */
+void ldpc_graph_destroy(ldpc_graph *g);
+
+/*
+ * Bytes of device workspace that ldpc_minsum_decode / ldpc_nms_decode need
+ * for B frames with the given flags (the kernel path depends on both).
+ * Returns 0 for g == NULL or B <= 0.
+ */
+size_t ldpc_decode_workspace_bytes(const ldpc_graph *g, int32_t B, uint32_t flags);
+
+/*
+ * Min-Sum decoding of B frames (Algorithm 1, with the pre-loop codeword test
+ * of the paper's kernel listing, Sec. IV).
+ *   llr_dev   B x n float32 channel LLRs.
+ *   B         frames, B >= 0 (B == 0 is a no-op).
+ *   max_iter  L >= 0 iterations at most.
+ *   flags     LDPC_* decode flags.
+ *   bits_dev  B x n uint8 out: hard decisions 0/1.
+ *   post_dev  B x n float32 out, may be NULL: posterior LLRs s_j.
+ *   iters_dev B int32 out: 0 if the channel decision is a codeword, else the
+ *             first iteration t after which the syndrome is zero, else L.
+ *             With LDPC_NO_EARLY_EXIT always L.
+ *   ok_dev    B uint8 out, may be NULL: 1 iff the final decision is a codeword.
+ *   ws_dev, ws_bytes  workspace of at least ldpc_decode_workspace_bytes(g, B,
+ *             flags) bytes, 256-byte aligned; its contents need not be set.
+ * Each iteration: every check sends each of its bits the product of the signs
+ * of the other bits' extrinsic values times the smallest of their magnitudes
+ * (eq. eta_update, computed through Observations 1 and 2); every bit sums its
+ * channel LLR and its incoming messages (eq. lambda_j, in ascending check
+ * order starting from +0, the channel LLR added last); the posteriors are
+ * sliced (eq. slice) and a frame stops once H b = 0.  A stopped frame's
+ * outputs are those of the iteration at which it stopped.  All arithmetic is
+ * IEEE binary32 with round-to-nearest-even and no contraction.
+ * Errors: LDPC_EINVAL (null g / llr / bits / iters with B > 0, B < 0,
+ * max_iter < 0), LDPC_EWORKSPACE, LDPC_EUNSUPPORTED, LDPC_EHIP.
+ */
+int ldpc_minsum_decode(const ldpc_graph *g, const float *llr_dev, int32_t B, int32_t max_iter,
+                       uint32_t flags, uint8_t *bits_dev, float *post_dev, int32_t *iters_dev,
+                       uint8_t *ok_dev, void *ws_dev, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Normalised / offset Min-Sum with learned weights (an extension; the paper
+ * decodes with plain Min-Sum).  Identical to ldpc_minsum_decode except that in
+ * iteration t (1-based) the message magnitude mu of a check row whose degree
+ * class is c (see ldpc_build_graph) becomes
+ *     max(fma(alpha[t-1][c], mu, -beta[t-1][c]), 0)
+ * before the sign is applied.  alpha = 1, beta = 0 everywhere reproduces
+ * ldpc_minsum_decode bit for bit.
+ *   alpha_dev, beta_dev  T x n_classes float32 device arrays, row-major.
+ *   T                    number of weight rows; requires max_iter <= T.
+ * Errors: as ldpc_minsum_decode, and LDPC_EINVAL for null weights, T < 1 or
+ * max_iter > T.
+ */
+int ldpc_nms_decode(const ldpc_graph *g, const float *llr_dev, int32_t B, int32_t max_iter, uint32_t flags,
+                    const float *alpha_dev, const float *beta_dev, int32_t T, uint8_t *bits_dev,
+                    float *post_dev, int32_t *iters_dev, uint8_t *ok_dev, void *ws_dev, size_t ws_bytes,
+                    hipStream_t stream);
+
+/*
+ * Per-kernel timing for benchmarks (decoding does not need it).
+ * ldpc_timing_enable(1) clears the record and starts bracketing every launch
+ * of the timed kernels with two HIP events on its launch stream (this adds
+ * event records to the stream and is not meant for graph capture);
+ * ldpc_timing_enable(0) clears and stops.  ldpc_timing_read waits for the
+ * recorded events and returns the summed elapsed milliseconds and the number
+ * of launches of one kernel since the last enable:
+ *   kernel 0  streaming check-node kernel
+ *   kernel 1  streaming bit-node kernel
+ *   kernel 2  on-chip whole-decode kernel
+ * Errors: LDPC_EINVAL (unknown kernel), LDPC_EHIP.
+ */
+int ldpc_timing_enable(int on);
+int ldpc_timing_read(int32_t kernel, double *total_ms, int64_t *launches);
+
+/* Text for a status code (static storage). */
+const char *ldpc_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LDPC_H */

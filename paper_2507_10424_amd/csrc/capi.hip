@@ -1,0 +1,58 @@
+// C-ABI entry points of libldpc: argument checks, workspace sizing and the
+// choice of kernel path.
+#include "ldpc_internal.h"
+
+namespace {
+
+int check_common(const ldpc_graph *g, const float *llr, int32_t B, int32_t L, uint8_t *bits, int32_t *iters) {
+    if (!g || B < 0 || L < 0) return LDPC_EINVAL;
+    if (B > 0 && (!llr || !bits || !iters)) return LDPC_EINVAL;
+    return LDPC_OK;
+}
+
+int decode(const ldpc_graph *g, const float *llr, int32_t B, int32_t L, uint32_t flags, const float *alpha,
+           const float *beta, int32_t T, uint8_t *bits, float *post, int32_t *iters, uint8_t *ok, void *ws,
+           size_t ws_bytes, hipStream_t stream) {
+    int st = check_common(g, llr, B, L, bits, iters);
+    if (st) return st;
+    if (B == 0) return LDPC_OK;
+    if (flags & LDPC_FORCE_ONCHIP) return LDPC_EUNSUPPORTED;
+    return ldpc::stream_decode(*g, llr, B, L, flags, alpha, beta, T, bits, post, iters, ok, ws, ws_bytes, stream);
+}
+
+} // namespace
+
+extern "C" size_t ldpc_decode_workspace_bytes(const ldpc_graph *g, int32_t B, uint32_t flags) {
+    (void)flags;
+    if (!g || B <= 0) return 0;
+    return ldpc::stream_workspace_bytes(*g, B);
+}
+
+extern "C" int ldpc_minsum_decode(const ldpc_graph *g, const float *llr_dev, int32_t B, int32_t max_iter,
+                                  uint32_t flags, uint8_t *bits_dev, float *post_dev, int32_t *iters_dev,
+                                  uint8_t *ok_dev, void *ws_dev, size_t ws_bytes, hipStream_t stream) {
+    return decode(g, llr_dev, B, max_iter, flags, nullptr, nullptr, 0, bits_dev, post_dev, iters_dev, ok_dev, ws_dev,
+                  ws_bytes, stream);
+}
+
+extern "C" int ldpc_nms_decode(const ldpc_graph *g, const float *llr_dev, int32_t B, int32_t max_iter, uint32_t flags,
+                               const float *alpha_dev, const float *beta_dev, int32_t T, uint8_t *bits_dev,
+                               float *post_dev, int32_t *iters_dev, uint8_t *ok_dev, void *ws_dev, size_t ws_bytes,
+                               hipStream_t stream) {
+    if (!alpha_dev || !beta_dev || T < 1 || max_iter > T) return LDPC_EINVAL;
+    return decode(g, llr_dev, B, max_iter, flags, alpha_dev, beta_dev, T, bits_dev, post_dev, iters_dev, ok_dev,
+                  ws_dev, ws_bytes, stream);
+}
+
+extern "C" const char *ldpc_status_string(int status) {
+    switch (status) {
+    case LDPC_OK: return "ok";
+    case LDPC_EINVAL: return "invalid argument";
+    case LDPC_EBADH: return "parity matrix not 0/1, has a row of degree 1, or too many ones";
+    case LDPC_ENOMEM: return "out of memory";
+    case LDPC_EHIP: return "HIP call or kernel launch failed";
+    case LDPC_EWORKSPACE: return "workspace missing or too small";
+    case LDPC_EUNSUPPORTED: return "graph exceeds a limit of the requested kernel path";
+    default: return "unknown status";
+    }
+}

@@ -1,0 +1,310 @@
+// HBM-streaming Min-Sum decoder: any code size, state in device memory.
+//
+// Layout ("frames in lanes"): frames are grouped in tiles of 64, one
+// wavefront per tile, lane = frame.  Every per-bit and per-edge quantity is
+// stored tile-major with the 64 frames innermost:
+//     r[tile][j][64], s[tile][j][64]  (channel LLR, posterior)   4 B each
+//     eta[tile][e][64]                (check-to-bit message)      4 B each
+// so each wavefront load or store of one edge or bit is 256 contiguous bytes,
+// whatever the structure of H.  The edge and bit indices are the same for
+// every lane, so they come in through scalar loads.
+//
+// One iteration is two launches (a kernel boundary is the grid-wide barrier
+// between the check and the bit phase):
+//   check kernel  per (row, frame): x_e = s_j - eta_e over the row (eta = 0 in
+//                 iteration 1, s = r), the row's two smallest |x|, the first
+//                 position of the smallest, the parity of the negative x,
+//                 then eta_e = (+-)(e == argmin ? min1 : min0) with the sign
+//                 from the parity without e's own sign (Observations 1, 2 of
+//                 Sec. III).  The XOR of the row's hard decisions of the s it
+//                 reads is the syndrome of the previous iteration.
+//   bit kernel    per (bit, frame): s_j = (+0 + eta_e over the column in
+//                 ascending check order) + r_j (eq. lambda_j), unless the
+//                 previous syndrome was zero: then the frame is finished and
+//                 keeps the s of that iteration.
+// The first check launch computes the syndrome of the channel decision, so a
+// frame whose channel decision is a codeword stops with 0 iterations (the
+// pre-loop test of the paper's kernel listing).
+#include "ldpc_internal.h"
+
+namespace ldpc {
+namespace {
+
+constexpr int kWaves = 4; // wavefronts per workgroup
+
+struct StreamWs {
+    float *r, *s, *eta;
+    uint32_t *done;     // frame has stopped (or is padding beyond B)
+    uint32_t *unsat[2]; // syndrome nonzero, indexed by iteration parity
+    int32_t *conv;      // iteration at which the frame stopped, -1 if not
+};
+
+size_t tiles_of(int32_t B) { return (size_t)((B + kTile - 1) / kTile); }
+
+StreamWs carve(const ldpc_graph &g, int32_t B, void *base, size_t *total) {
+    const size_t nt = tiles_of(B);
+    const size_t fr = nt * kTile;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes, 256);
+        return o;
+    };
+    const size_t o_r = take(nt * (size_t)g.n * kTile * 4);
+    const size_t o_s = take(nt * (size_t)g.n * kTile * 4);
+    const size_t o_e = take(nt * (size_t)g.E * kTile * 4);
+    const size_t o_d = take(fr * 4);
+    const size_t o_u0 = take(fr * 4);
+    const size_t o_u1 = take(fr * 4);
+    const size_t o_c = take(fr * 4);
+    if (total) *total = off;
+    StreamWs w{};
+    char *b = (char *)base;
+    if (b) {
+        w.r = (float *)(b + o_r);
+        w.s = (float *)(b + o_s);
+        w.eta = (float *)(b + o_e);
+        w.done = (uint32_t *)(b + o_d);
+        w.unsat[0] = (uint32_t *)(b + o_u0);
+        w.unsat[1] = (uint32_t *)(b + o_u1);
+        w.conv = (int32_t *)(b + o_c);
+    }
+    return w;
+}
+
+__global__ void k_flags_init(int32_t B, int32_t frames, uint32_t *done, uint32_t *u0, uint32_t *u1, int32_t *conv) {
+    const int32_t f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= frames) return;
+    done[f] = f >= B;
+    u0[f] = 0;
+    u1[f] = 0;
+    conv[f] = -1;
+}
+
+// llr[B][n] -> r[tile][j][64] through a 64 x 64 LDS tile.
+__global__ __launch_bounds__(256) void k_to_tiles(const float *__restrict__ llr, int32_t B, int32_t n,
+                                                  float *__restrict__ r) {
+    __shared__ float t[kTile][kTile + 1];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int32_t nchunks = (n + 63) / 64;
+    const int32_t tile = blockIdx.x / nchunks, j0 = (blockIdx.x % nchunks) * 64;
+#pragma unroll 4
+    for (int k = w; k < kTile; k += kWaves) {
+        const int64_t f = (int64_t)tile * kTile + k;
+        const int32_t j = j0 + lane;
+        t[k][lane] = (f < B && j < n) ? llr[f * n + j] : 0.0f;
+    }
+    __syncthreads();
+    float *rt = r + (size_t)tile * n * kTile;
+#pragma unroll 4
+    for (int k = w; k < kTile; k += kWaves) {
+        const int32_t j = j0 + k;
+        if (j < n) rt[(size_t)j * kTile + lane] = t[lane][k];
+    }
+}
+
+// One wavefront = one check row x one frame tile.  `t` is the iteration
+// being computed (1-based).
+__global__ __launch_bounds__(256) void k_check(const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx,
+                                               const int32_t *__restrict__ row_class, int32_t m, int32_t n, int64_t E,
+                                               int32_t B, int32_t row_blocks, const float *__restrict__ r,
+                                               const float *__restrict__ s, float *__restrict__ eta,
+                                               const uint32_t *__restrict__ done, uint32_t *__restrict__ unsat,
+                                               int32_t t, const float *__restrict__ alpha,
+                                               const float *__restrict__ beta, int32_t n_classes) {
+    const uint32_t bid = xcd_swizzle(blockIdx.x, gridDim.x);
+    const int32_t tile = bid / row_blocks;
+    const int32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int32_t row = (bid % row_blocks) * kWaves + w;
+    const int lane = threadIdx.x & 63;
+    const int32_t f = tile * kTile + lane;
+    const bool act = !done[f];
+    if (row >= m || !__any(act)) return;
+
+    const float *sv = (t == 1 ? r : s) + (size_t)tile * n * kTile + lane;
+    float *et = eta + (size_t)tile * E * kTile + lane;
+    const int32_t e0 = row_ptr[row], e1 = row_ptr[row + 1];
+
+    float min0 = __builtin_inff(), min1 = __builtin_inff();
+    int32_t am = -1;
+    uint32_t negs = 0, par = 0, syn = 0;
+    for (int32_t e = e0; e < e1; ++e) {
+        const float sj = sv[(size_t)col_idx[e] * kTile];
+        syn ^= sj < 0.0f;
+        const float x = (t == 1) ? sj : sj - et[(size_t)e * kTile];
+        const float a = fabsf(x);
+        const uint32_t ng = x < 0.0f;
+        par ^= ng;
+        const int32_t k = e - e0;
+        if (k < 32) negs |= ng << k;
+        if (a < min0) {
+            min1 = min0;
+            min0 = a;
+            am = k;
+        } else if (a < min1) {
+            min1 = a;
+        }
+    }
+    if (alpha != nullptr && e1 > e0) {
+        const int32_t c = row_class[row];
+        const float al = alpha[(t - 1) * n_classes + c], be = beta[(t - 1) * n_classes + c];
+        const float v0 = fmaf(al, min0, -be), v1 = fmaf(al, min1, -be);
+        min0 = v0 > 0.0f ? v0 : 0.0f;
+        min1 = v1 > 0.0f ? v1 : 0.0f;
+    }
+    for (int32_t e = e0; e < e1; ++e) {
+        const int32_t k = e - e0;
+        uint32_t ng;
+        if (k < 32) {
+            ng = (negs >> k) & 1u;
+        } else { // rows longer than 32: recompute the sign of x (inputs unchanged so far)
+            const float sj = sv[(size_t)col_idx[e] * kTile];
+            const float x = (t == 1) ? sj : sj - et[(size_t)e * kTile];
+            ng = x < 0.0f;
+        }
+        const float mag = (k == am) ? min1 : min0;
+        if (act) et[(size_t)e * kTile] = (par ^ ng) ? -mag : mag;
+    }
+    if (act && syn) unsat[f] = 1u;
+}
+
+// One wavefront = one bit column x one frame tile.
+__global__ __launch_bounds__(256) void k_bit(const int32_t *__restrict__ col_ptr, const int32_t *__restrict__ csc_edge,
+                                             int32_t n, int64_t E, int32_t col_blocks, const float *__restrict__ r,
+                                             float *__restrict__ s, const float *__restrict__ eta,
+                                             uint32_t *__restrict__ done, const uint32_t *__restrict__ unsat_cur,
+                                             uint32_t *__restrict__ unsat_next, int32_t *__restrict__ conv, int32_t t,
+                                             int32_t early) {
+    const uint32_t bid = xcd_swizzle(blockIdx.x, gridDim.x);
+    const int32_t tile = bid / col_blocks;
+    const int32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int32_t cb = bid % col_blocks;
+    const int32_t col = cb * kWaves + w;
+    const int lane = threadIdx.x & 63;
+    const int32_t f = tile * kTile + lane;
+    bool act = !done[f];
+    if (col >= n || !__any(act)) return;
+    const bool stop = act && early && unsat_cur[f] == 0u;
+    if (cb == 0 && w == 0) { // the wavefront of column 0 keeps the per-frame flags
+        if (stop) {
+            done[f] = 1u;
+            conv[f] = t - 1;
+        } else if (act) {
+            unsat_next[f] = 0u;
+        }
+    }
+    act = act && !stop;
+    if (!__any(act)) return;
+    const float *et = eta + (size_t)tile * E * kTile + lane;
+    float acc = 0.0f;
+    const int32_t k0 = col_ptr[col], k1 = col_ptr[col + 1];
+    for (int32_t k = k0; k < k1; ++k) acc = acc + et[(size_t)csc_edge[k] * kTile];
+    const size_t o = ((size_t)tile * n + col) * kTile + lane;
+    if (act) s[o] = acc + r[o];
+}
+
+// Syndrome of the current decision only (after the last iteration).
+__global__ __launch_bounds__(256) void k_syndrome(const int32_t *__restrict__ row_ptr,
+                                                  const int32_t *__restrict__ col_idx, int32_t m, int32_t n,
+                                                  int32_t row_blocks, const float *__restrict__ sv_all,
+                                                  const uint32_t *__restrict__ done, uint32_t *__restrict__ unsat) {
+    const uint32_t bid = xcd_swizzle(blockIdx.x, gridDim.x);
+    const int32_t tile = bid / row_blocks;
+    const int32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int32_t row = (bid % row_blocks) * kWaves + w;
+    const int lane = threadIdx.x & 63;
+    const int32_t f = tile * kTile + lane;
+    const bool act = !done[f];
+    if (row >= m || !__any(act)) return;
+    const float *sv = sv_all + (size_t)tile * n * kTile + lane;
+    uint32_t syn = 0;
+    for (int32_t e = row_ptr[row]; e < row_ptr[row + 1]; ++e) syn ^= sv[(size_t)col_idx[e] * kTile] < 0.0f;
+    if (act && syn) unsat[f] = 1u;
+}
+
+// Per frame: iterations and convergence flag.
+__global__ void k_finalize(int32_t B, int32_t L, const int32_t *__restrict__ conv,
+                           const uint32_t *__restrict__ unsat_final, int32_t *__restrict__ iters,
+                           uint8_t *__restrict__ ok) {
+    const int32_t f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= B) return;
+    const int32_t c = conv[f];
+    iters[f] = c >= 0 ? c : L;
+    if (ok) ok[f] = (c >= 0 || unsat_final[f] == 0u) ? 1 : 0;
+}
+
+// s (or r for frames that stopped at iteration 0) -> post[B][n], bits[B][n].
+__global__ __launch_bounds__(256) void k_from_tiles(const float *__restrict__ r, const float *__restrict__ s,
+                                                    const int32_t *__restrict__ conv, int32_t B, int32_t n,
+                                                    int32_t L, float *__restrict__ post, uint8_t *__restrict__ bits) {
+    __shared__ float t[kTile][kTile + 1];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int32_t nchunks = (n + 63) / 64;
+    const int32_t tile = blockIdx.x / nchunks, j0 = (blockIdx.x % nchunks) * 64;
+    const int32_t f_lane = tile * kTile + lane;
+    const bool use_r = L == 0 || (f_lane < B && conv[f_lane] == 0);
+    const float *src = (use_r ? r : s) + (size_t)tile * n * kTile;
+#pragma unroll 4
+    for (int k = w; k < kTile; k += kWaves) {
+        const int32_t j = j0 + k;
+        t[lane][k] = (j < n) ? src[(size_t)j * kTile + lane] : 0.0f;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int k = w; k < kTile; k += kWaves) {
+        const int64_t f = (int64_t)tile * kTile + k;
+        const int32_t j = j0 + lane;
+        if (f < B && j < n) {
+            const float v = t[k][lane];
+            if (post) post[f * n + j] = v;
+            bits[f * n + j] = v < 0.0f ? 1 : 0;
+        }
+    }
+}
+
+} // namespace
+
+size_t stream_workspace_bytes(const ldpc_graph &g, int32_t B) {
+    size_t total = 0;
+    carve(g, B, nullptr, &total);
+    return total;
+}
+
+int stream_decode(const ldpc_graph &g, const float *llr, int32_t B, int32_t L, uint32_t flags, const float *alpha,
+                  const float *beta, int32_t T, uint8_t *bits, float *post, int32_t *iters, uint8_t *ok, void *ws,
+                  size_t ws_bytes, hipStream_t stream) {
+    (void)T;
+    size_t need = 0;
+    StreamWs w = carve(g, B, ws, &need);
+    if (ws == nullptr || ws_bytes < need) return LDPC_EWORKSPACE;
+    const int32_t nt = (int32_t)tiles_of(B);
+    const int32_t frames = nt * kTile;
+    const int32_t early = (flags & LDPC_NO_EARLY_EXIT) ? 0 : 1;
+    const int32_t row_blocks = (g.m + kWaves - 1) / kWaves;
+    const int32_t col_blocks = (g.n + kWaves - 1) / kWaves;
+    const int32_t nchunks = (g.n + 63) / 64;
+    const int32_t ncls = (int32_t)g.class_degrees.size();
+
+    k_flags_init<<<(frames + 255) / 256, 256, 0, stream>>>(B, frames, w.done, w.unsat[0], w.unsat[1], w.conv);
+    k_to_tiles<<<nt * nchunks, 256, 0, stream>>>(llr, B, g.n, w.r);
+    for (int32_t t = 1; t <= L; ++t) {
+        timed_launch(K_CHECK, stream, [&] {
+            k_check<<<nt * row_blocks, 256, 0, stream>>>(g.row_ptr, g.col_idx, g.row_class, g.m, g.n, g.E, B,
+                                                         row_blocks, w.r, w.s, w.eta, w.done, w.unsat[t & 1], t,
+                                                         alpha, beta, ncls);
+        });
+        timed_launch(K_BIT, stream, [&] {
+            k_bit<<<nt * col_blocks, 256, 0, stream>>>(g.col_ptr, g.csc_edge, g.n, g.E, col_blocks, w.r, w.s, w.eta,
+                                                       w.done, w.unsat[t & 1], w.unsat[(t + 1) & 1], w.conv, t,
+                                                       early);
+        });
+    }
+    uint32_t *unsat_final = w.unsat[(L + 1) & 1];
+    k_syndrome<<<nt * row_blocks, 256, 0, stream>>>(g.row_ptr, g.col_idx, g.m, g.n, row_blocks, L == 0 ? w.r : w.s,
+                                                    w.done, unsat_final);
+    k_finalize<<<(B + 255) / 256, 256, 0, stream>>>(B, L, w.conv, unsat_final, iters, ok);
+    k_from_tiles<<<nt * nchunks, 256, 0, stream>>>(w.r, w.s, w.conv, B, g.n, L, post, bits);
+    return hipGetLastError() == hipSuccess ? LDPC_OK : LDPC_EHIP;
+}
+
+} // namespace ldpc

@@ -1,0 +1,270 @@
+// Tanner graph construction from a dense parity matrix on the device.
+//
+// The neighbour sets of Sec. II-B: N_i (the bits of check row i, the ones of
+// row i of H) and M_j (the checks of bit j, the ones of column j).  They are
+// stored as CSR (row_ptr, col_idx) and as a CSC view (col_ptr, csc_edge) that
+// points back into the CSR edge numbering, so one per-edge message array
+// serves both the check update (row order) and the bit update (column order).
+#include <algorithm>
+#include <cstring>
+
+#include "ldpc_internal.h"
+
+namespace {
+
+__device__ __forceinline__ int wave_sum(int v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// One wavefront per row: count the ones of the row and flag entries > 1.
+__global__ __launch_bounds__(256) void k_row_count(const uint8_t *__restrict__ H, int32_t m, int32_t n,
+                                                   int32_t *__restrict__ row_deg, int32_t *__restrict__ bad) {
+    const int lane = threadIdx.x & 63;
+    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= m) return;
+    const uint8_t *h = H + row * (int64_t)n;
+    int cnt = 0, big = 0;
+    for (int32_t k = lane; k < n; k += 64) {
+        const uint8_t v = h[k];
+        cnt += v;
+        big |= v > 1;
+    }
+    cnt = wave_sum(cnt);
+    big = wave_sum(big);
+    if (lane == 0) {
+        row_deg[row] = cnt;
+        if (big) atomicOr(bad, 1);
+    }
+}
+
+// One wavefront per row: write the bit index of every one, ascending, by a
+// ballot over each 64-entry chunk and a popcount of the lower lanes.
+__global__ __launch_bounds__(256) void k_row_fill(const uint8_t *__restrict__ H, int32_t m, int32_t n,
+                                                  const int32_t *__restrict__ row_ptr,
+                                                  int32_t *__restrict__ col_idx) {
+    const int lane = threadIdx.x & 63;
+    const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (row >= m) return;
+    const uint8_t *h = H + row * (int64_t)n;
+    int32_t out = row_ptr[row];
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    for (int32_t base = 0; base < n; base += 64) {
+        const int32_t k = base + lane;
+        const bool one = k < n && h[k] != 0;
+        const uint64_t mask = __ballot(one);
+        if (one) col_idx[out + __popcll(mask & below)] = k;
+        out += __popcll(mask);
+    }
+}
+
+__global__ void k_col_count(const int32_t *__restrict__ col_idx, int64_t E, int32_t *__restrict__ col_deg) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < E) atomicAdd(&col_deg[col_idx[e]], 1);
+}
+
+// Scatter every edge into its column's segment (slot order arbitrary) ...
+__global__ void k_csc_scatter(const int32_t *__restrict__ col_idx, int64_t E, const int32_t *__restrict__ col_ptr,
+                              int32_t *__restrict__ fill, int32_t *__restrict__ csc_edge) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    const int32_t j = col_idx[e];
+    const int32_t slot = atomicAdd(&fill[j], 1);
+    csc_edge[col_ptr[j] + slot] = (int32_t)e;
+}
+
+// ... then sort each segment: CSR numbers grow with the row index, so an
+// ascending segment lists the column's checks in ascending order.
+__global__ void k_csc_sort(const int32_t *__restrict__ col_ptr, int32_t n, int32_t *__restrict__ csc_edge) {
+    const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const int32_t a = col_ptr[j], b = col_ptr[j + 1];
+    for (int32_t p = a + 1; p < b; ++p) {
+        const int32_t v = csc_edge[p];
+        int32_t q = p - 1;
+        while (q >= a && csc_edge[q] > v) {
+            csc_edge[q + 1] = csc_edge[q];
+            --q;
+        }
+        csc_edge[q + 1] = v;
+    }
+}
+
+__global__ void k_edge_pos(const int32_t *__restrict__ csc_edge, int64_t E, int32_t *__restrict__ edge_pos) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < E) edge_pos[csc_edge[k]] = (int32_t)k;
+}
+
+void free_graph_arrays(ldpc_graph *g) {
+    if (!g) return;
+    (void)hipFree(g->row_ptr);
+    (void)hipFree(g->col_idx);
+    (void)hipFree(g->col_ptr);
+    (void)hipFree(g->csc_edge);
+    (void)hipFree(g->row_class);
+    (void)hipFree(g->edge_pos);
+    g->row_ptr = g->col_idx = g->col_ptr = g->csc_edge = g->row_class = g->edge_pos = nullptr;
+}
+
+template <class T> hipError_t dalloc(T **p, size_t count) {
+    return hipMalloc((void **)p, sizeof(T) * std::max<size_t>(count, 1));
+}
+
+int build(const uint8_t *H, int32_t m, int32_t n, hipStream_t s, ldpc_graph *g) {
+    int32_t *row_deg = nullptr, *bad = nullptr, *col_deg = nullptr, *fill = nullptr;
+    int status = LDPC_OK;
+    auto fail = [&](int st) {
+        status = st;
+        return st;
+    };
+    std::vector<int32_t> h_row(m), h_col(n);
+    int32_t h_bad = 0;
+    int64_t E = 0;
+    do {
+        if (dalloc(&row_deg, m) != hipSuccess || dalloc(&bad, 1) != hipSuccess ||
+            dalloc(&col_deg, n) != hipSuccess || dalloc(&fill, n) != hipSuccess) {
+            fail(LDPC_ENOMEM);
+            break;
+        }
+        if (hipMemsetAsync(bad, 0, sizeof(int32_t), s) != hipSuccess) { fail(LDPC_EHIP); break; }
+        k_row_count<<<(m + 3) / 4, 256, 0, s>>>(H, m, n, row_deg, bad);
+        if (hipGetLastError() != hipSuccess ||
+            hipMemcpyAsync(h_row.data(), row_deg, sizeof(int32_t) * m, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipMemcpyAsync(&h_bad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            fail(LDPC_EHIP);
+            break;
+        }
+        if (h_bad) { fail(LDPC_EBADH); break; }
+        std::vector<int32_t> h_rowptr(m + 1);
+        int32_t dcmax = 0;
+        std::vector<uint8_t> present(n + 1, 0);
+        for (int32_t i = 0; i < m; ++i) {
+            h_rowptr[i] = (int32_t)E;
+            E += h_row[i];
+            dcmax = std::max(dcmax, h_row[i]);
+            present[h_row[i]] = 1;
+        }
+        bool deg1 = false;
+        for (int32_t i = 0; i < m; ++i) deg1 |= h_row[i] == 1;
+        if (deg1 || E >= INT32_MAX) { fail(LDPC_EBADH); break; }
+        h_rowptr[m] = (int32_t)E;
+        g->E = E;
+        g->dc_max = dcmax;
+        std::vector<int32_t> rank(n + 1, -1);
+        g->class_degrees.clear();
+        for (int32_t d = 1; d <= n; ++d)
+            if (present[d]) {
+                rank[d] = (int32_t)g->class_degrees.size();
+                g->class_degrees.push_back(d);
+            }
+        std::vector<int32_t> h_class(m);
+        for (int32_t i = 0; i < m; ++i) h_class[i] = h_row[i] ? rank[h_row[i]] : -1;
+
+        if (dalloc(&g->row_ptr, m + 1) != hipSuccess || dalloc(&g->col_idx, E) != hipSuccess ||
+            dalloc(&g->col_ptr, n + 1) != hipSuccess || dalloc(&g->csc_edge, E) != hipSuccess ||
+            dalloc(&g->row_class, m) != hipSuccess || dalloc(&g->edge_pos, E) != hipSuccess) {
+            fail(LDPC_ENOMEM);
+            break;
+        }
+        if (hipMemcpyAsync(g->row_ptr, h_rowptr.data(), sizeof(int32_t) * (m + 1), hipMemcpyHostToDevice, s) !=
+                hipSuccess ||
+            hipMemcpyAsync(g->row_class, h_class.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice, s) !=
+                hipSuccess ||
+            hipMemsetAsync(col_deg, 0, sizeof(int32_t) * n, s) != hipSuccess ||
+            hipMemsetAsync(fill, 0, sizeof(int32_t) * n, s) != hipSuccess) {
+            fail(LDPC_EHIP);
+            break;
+        }
+        k_row_fill<<<(m + 3) / 4, 256, 0, s>>>(H, m, n, g->row_ptr, g->col_idx);
+        const unsigned eblocks = (unsigned)((E + 255) / 256);
+        if (E > 0) k_col_count<<<eblocks, 256, 0, s>>>(g->col_idx, E, col_deg);
+        if (hipGetLastError() != hipSuccess ||
+            hipMemcpyAsync(h_col.data(), col_deg, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            fail(LDPC_EHIP);
+            break;
+        }
+        std::vector<int32_t> h_colptr(n + 1);
+        int32_t dvmax = 0;
+        int64_t acc = 0;
+        for (int32_t j = 0; j < n; ++j) {
+            h_colptr[j] = (int32_t)acc;
+            acc += h_col[j];
+            dvmax = std::max(dvmax, h_col[j]);
+        }
+        h_colptr[n] = (int32_t)acc;
+        g->dv_max = dvmax;
+        if (hipMemcpyAsync(g->col_ptr, h_colptr.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, s) !=
+            hipSuccess) {
+            fail(LDPC_EHIP);
+            break;
+        }
+        if (E > 0) {
+            k_csc_scatter<<<eblocks, 256, 0, s>>>(g->col_idx, E, g->col_ptr, fill, g->csc_edge);
+            k_csc_sort<<<(n + 255) / 256, 256, 0, s>>>(g->col_ptr, n, g->csc_edge);
+            k_edge_pos<<<eblocks, 256, 0, s>>>(g->csc_edge, E, g->edge_pos);
+        }
+        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+            fail(LDPC_EHIP);
+            break;
+        }
+    } while (false);
+    (void)hipFree(row_deg);
+    (void)hipFree(bad);
+    (void)hipFree(col_deg);
+    (void)hipFree(fill);
+    return status;
+}
+
+} // namespace
+
+extern "C" int ldpc_build_graph(const uint8_t *H_dev, int32_t m, int32_t n, hipStream_t stream,
+                                ldpc_graph **out) {
+    if (!out) return LDPC_EINVAL;
+    *out = nullptr;
+    if (!H_dev || m < 1 || n < 1) return LDPC_EINVAL;
+    ldpc_graph *g = new (std::nothrow) ldpc_graph();
+    if (!g) return LDPC_ENOMEM;
+    g->m = m;
+    g->n = n;
+    if (hipGetDevice(&g->device) != hipSuccess) {
+        delete g;
+        return LDPC_EHIP;
+    }
+    const int st = build(H_dev, m, n, stream, g);
+    if (st != LDPC_OK) {
+        (void)hipStreamSynchronize(stream);
+        free_graph_arrays(g);
+        delete g;
+        return st;
+    }
+    *out = g;
+    return LDPC_OK;
+}
+
+extern "C" int ldpc_graph_info(const ldpc_graph *g, int32_t *m, int32_t *n, int64_t *n_edges, int32_t *dc_max,
+                               int32_t *dv_max, int32_t *n_classes, int32_t *check_degrees, int32_t cap) {
+    if (!g) return LDPC_EINVAL;
+    if (m) *m = g->m;
+    if (n) *n = g->n;
+    if (n_edges) *n_edges = g->E;
+    if (dc_max) *dc_max = g->dc_max;
+    if (dv_max) *dv_max = g->dv_max;
+    if (n_classes) *n_classes = (int32_t)g->class_degrees.size();
+    if (check_degrees)
+        for (int32_t k = 0; k < cap && k < (int32_t)g->class_degrees.size(); ++k) check_degrees[k] = g->class_degrees[k];
+    return LDPC_OK;
+}
+
+extern "C" void ldpc_graph_destroy(ldpc_graph *g) {
+    if (!g) return;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(g->device);
+    (void)hipDeviceSynchronize();
+    free_graph_arrays(g);
+    (void)hipSetDevice(cur);
+    delete g;
+}

@@ -1,0 +1,81 @@
+// Internal declarations of libldpc (not part of the C-ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "ldpc.h"
+
+// Device-side Tanner graph.  Edges are numbered row by row (CSR order), bits
+// ascending inside a row; the CSC side lists, for every bit, the CSR numbers
+// of its edges in ascending check index.
+struct ldpc_graph {
+    int device = 0;
+    int32_t m = 0, n = 0;
+    int64_t E = 0;
+    int32_t dc_max = 0, dv_max = 0;
+    std::vector<int32_t> class_degrees; // distinct nonzero row degrees, ascending
+    int32_t *row_ptr = nullptr;   // m + 1
+    int32_t *col_idx = nullptr;   // E: bit of each edge
+    int32_t *col_ptr = nullptr;   // n + 1
+    int32_t *csc_edge = nullptr;  // E: CSR edge number of the k-th CSC entry
+    int32_t *row_class = nullptr; // m: degree class of the row (-1 for degree 0)
+    int32_t *edge_pos = nullptr;  // E: CSC slot of each CSR edge (inverse of csc_edge)
+};
+
+#define LDPC_HIP_TRY(expr)                                   \
+    do {                                                     \
+        if ((expr) != hipSuccess) return LDPC_EHIP;          \
+    } while (0)
+
+namespace ldpc {
+
+constexpr int kTile = 64; // frames per tile of the streaming layout (one wavefront)
+
+// Streaming (HBM-resident) decoder: workspace bytes and launch sequence.
+size_t stream_workspace_bytes(const ldpc_graph &g, int32_t B);
+int stream_decode(const ldpc_graph &g, const float *llr, int32_t B, int32_t L, uint32_t flags,
+                  const float *alpha, const float *beta, int32_t T, uint8_t *bits, float *post,
+                  int32_t *iters, uint8_t *ok, void *ws, size_t ws_bytes, hipStream_t stream);
+
+// Kernel ids of the optional per-kernel timing (ldpc_timing_read).
+enum KernelId { K_CHECK = 0, K_BIT = 1, K_ONCHIP = 2, K_COUNT = 3 };
+bool timing_on();
+void timing_record(int kid, hipEvent_t a, hipEvent_t b);
+
+// Launch `fn` (which enqueues one kernel on `s`); when timing is enabled,
+// bracket it with two events on the same stream.
+template <class F> inline void timed_launch(int kid, hipStream_t s, F &&fn) {
+    if (!timing_on()) {
+        fn();
+        return;
+    }
+    hipEvent_t a = nullptr, b = nullptr;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+        fn();
+        return;
+    }
+    (void)hipEventRecord(a, s);
+    fn();
+    (void)hipEventRecord(b, s);
+    timing_record(kid, a, b);
+}
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Linear workgroup id -> logical id such that consecutive logical ids stay on
+// one XCD.  Workgroups are dealt to the 8 XCDs round-robin, so XCD x runs the
+// ids x, x+8, x+16, ...; mapping them to a contiguous logical range keeps the
+// blocks that share data (one frame tile) inside one XCD's L2.
+__device__ __forceinline__ uint32_t xcd_swizzle(uint32_t bid, uint32_t nblocks) {
+    constexpr uint32_t kXcd = 8;
+    const uint32_t per = nblocks / kXcd; // blocks per XCD in the full part
+    const uint32_t full = per * kXcd;
+    if (bid >= full) return bid;         // ragged tail keeps its id
+    return (bid % kXcd) * per + bid / kXcd;
+}
+
+} // namespace ldpc

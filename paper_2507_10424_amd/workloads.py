@@ -275,6 +275,24 @@ class gf2_encoder:
             c[b0:b0 + step][:, self.pivots] = (par.astype(np.int64) & 1).astype(np.uint8)
         return c
 
+    def random_codewords_torch(self, B: int, seed: int, device):
+        """Random codewords generated on ``device`` with torch (seeded
+        Philox on a GPU): (B, n) uint8 tensor."""
+        import torch
+        gen = torch.Generator(device=device)
+        gen.manual_seed(int(seed))
+        info = torch.randint(0, 2, (B, self.k), generator=gen, device=device, dtype=torch.uint8)
+        P = torch.from_numpy(self._P.astype(np.float64)).to(device)
+        free = torch.from_numpy(self.free).to(device)
+        piv = torch.from_numpy(self.pivots).to(device)
+        c = torch.zeros((B, self.n), dtype=torch.uint8, device=device)
+        c[:, free] = info
+        step = 16384
+        for b0 in range(0, B, step):
+            par = info[b0:b0 + step].to(torch.float64) @ P.T  # exact: integer sums < 2^53
+            c[b0:b0 + step, piv] = torch.remainder(par, 2.0).to(torch.uint8)
+        return c
+
     def random_codewords(self, B: int, seed: int) -> np.ndarray:
         rng = np.random.default_rng(seed)
         info = rng.integers(0, 2, size=(B, self.k), dtype=np.uint8)
@@ -284,6 +302,21 @@ class gf2_encoder:
 # --------------------------------------------------------------------------
 # Channel
 # --------------------------------------------------------------------------
+
+def bpsk_awgn_llr_torch(codewords, ebn0_db: float, rate: float, seed: int, device, n: int | None = None,
+                        batch: int | None = None):
+    """Channel LLRs generated on ``device`` with torch (seeded Philox
+    normals): float32 (B, n) tensor.  ``codewords=None`` with ``batch``, ``n``
+    gives the all-zero codeword."""
+    import torch
+    sigma = sigma_for_ebn0(ebn0_db, rate)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    shape = (batch, n) if codewords is None else tuple(codewords.shape)
+    noise = torch.randn(shape, generator=gen, device=device, dtype=torch.float32)
+    x = 1.0 if codewords is None else 1.0 - 2.0 * codewords.to(torch.float32)
+    return ((x + sigma * noise) * (2.0 / (sigma * sigma))).to(torch.float32).contiguous()
+
 
 def sigma_for_ebn0(ebn0_db: float, rate: float) -> float:
     return float(np.sqrt(1.0 / (2.0 * rate * 10.0 ** (ebn0_db / 10.0))))

@@ -1,0 +1,144 @@
+"""HIP path vs the CPU oracle, element by element, through the C-ABI."""
+import numpy as np
+import pytest
+
+from paper_2507_10424_amd import workloads as wl
+from parity import assert_parity, check, gpu_decode, note, oracle_decode
+
+pytestmark = pytest.mark.gpu
+
+PATHS = {"stream": 2}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2507_10424_amd import ldpc
+    ldpc.load_library()
+
+
+@pytest.mark.parametrize("path", sorted(PATHS))
+def test_small_regular_code_full(path):
+    """(3,6) Gallager code n=96, 1000 all-zero frames at Eb/N0 = 2 dB, L = 20."""
+    H = wl.regular_ldpc(96, 48, 3, 6, seed=1)
+    llr = wl.bpsk_awgn_llr(None, 2.0, 0.5, seed=100, n=96, batch=1000)
+    check(H, llr, 20, PATHS[path], what=f"C0 {path}")
+
+
+@pytest.mark.parametrize("path", sorted(PATHS))
+@pytest.mark.parametrize("B", [1, 63, 64, 65, 130])
+def test_ragged_batches(path, B):
+    H = wl.regular_ldpc(96, 48, 3, 6, seed=1)
+    enc = wl.gf2_encoder(H)
+    cw = enc.random_codewords(B, seed=B)
+    llr = wl.bpsk_awgn_llr(cw, 1.5, 0.5, seed=B + 1)
+    check(H, llr, 15, PATHS[path], what=f"ragged {path}")
+
+
+@pytest.mark.parametrize("path", sorted(PATHS))
+@pytest.mark.parametrize("L", [0, 1, 2])
+@pytest.mark.parametrize("flags", [0, 1])
+def test_iteration_limits(path, L, flags):
+    H = wl.regular_ldpc(96, 48, 3, 6, seed=1)
+    llr = wl.bpsk_awgn_llr(None, 1.0, 0.5, seed=7, n=96, batch=200)
+    check(H, llr, L, PATHS[path] | flags, what=f"L={L} {path}")
+
+
+@pytest.mark.parametrize("path", sorted(PATHS))
+def test_paper_example_codewords(path):
+    from oracle_pins import codebook
+    H = wl.paper_tanner_example()
+    book = codebook(H)
+    r = (1.5 * (1.0 - 2.0 * book.astype(np.float32))).astype(np.float32)
+    gpu, _ = check(H, r, 10, PATHS[path], what="paper 5x10 codewords")
+    assert np.all(gpu[2] == 0) and np.array_equal(gpu[0], book) and np.array_equal(gpu[1], r)
+
+
+@pytest.mark.parametrize("path", sorted(PATHS))
+@pytest.mark.parametrize("seed", range(6))
+def test_irregular_codes(path, seed):
+    """Irregular degrees, bits of degree 0, rows longer than 32."""
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(40, 300))
+    m = int(rng.integers(n // 6, n // 2))
+    H = wl.random_irregular_code(n, m, seed=seed, dv_choices=(0, 1, 2, 3, 4, 6, 9), max_row_degree=64)
+    if seed % 2 == 0:
+        H = np.vstack([H, np.zeros((1, n), np.uint8)])  # a row of degree 0
+    llr = rng.normal(1.0, 1.3, size=(int(rng.integers(50, 260)), n)).astype(np.float32)
+    check(H, llr, 25, PATHS[path], what=f"irregular {seed} {path}")
+    check(H, llr, 25, PATHS[path] | 1, what=f"irregular {seed} {path} no-exit")
+
+
+@pytest.mark.parametrize("path", sorted(PATHS))
+def test_long_rows(path):
+    """Check rows of degree 30..60 (beyond a 32-bit sign mask)."""
+    H = wl.random_irregular_code(300, 8, seed=9, dv_choices=(1, 2), max_row_degree=64)
+    assert H.sum(1).max() > 32
+    llr = np.random.default_rng(9).normal(1.5, 1.0, size=(150, 300)).astype(np.float32)
+    check(H, llr, 20, PATHS[path], what="long rows")
+    check(H, llr, 20, PATHS[path] | 1, what="long rows no-exit")
+
+
+@pytest.mark.parametrize("path", sorted(PATHS))
+def test_tree_codes_no_early_exit(path):
+    for seed in range(12):
+        H = wl.tree_code(2 + seed % 6, seed=1000 + seed, max_check_degree=2 + seed % 4)
+        m, n = H.shape
+        llr = np.random.default_rng(seed).normal(0.5, 1.5, size=(70, n)).astype(np.float32)
+        check(H, llr, n + m, PATHS[path] | 1, what=f"tree {seed}")
+
+
+@pytest.mark.parametrize("path", sorted(PATHS))
+def test_adversarial_llrs(path):
+    """Exact ties between magnitudes, signed zeros, extreme scales."""
+    H = wl.regular_ldpc(96, 48, 3, 6, seed=1)
+    rng = np.random.default_rng(3)
+    vals = np.array([1.0, -1.0, 2.0, -2.0, 0.5, -0.5, 0.0, -0.0], np.float32)
+    a = vals[rng.integers(0, vals.size, size=(300, 96))]
+    a[:100] += np.float32(1.0)  # mostly positive, still many ties
+    b = a * np.float32(2.0 ** 60)
+    c = a * np.float32(2.0 ** -60)
+    d = np.zeros((10, 96), np.float32)
+    e = -np.zeros((10, 96), np.float32)
+    for name, llr in [("ties", a), ("huge", b), ("tiny", c), ("zeros", d), ("negzeros", e)]:
+        check(H, llr, 20, PATHS[path], what=f"adversarial {name}")
+
+
+@pytest.mark.parametrize("path", sorted(PATHS))
+def test_nms_weights(path):
+    H = wl.random_irregular_code(120, 60, seed=4, dv_choices=(2, 3, 4))
+    import oracle
+    C = oracle.check_degrees(H).size
+    rng = np.random.default_rng(5)
+    T = 12
+    alpha = rng.uniform(0.5, 1.2, size=(T, C)).astype(np.float32)
+    beta = rng.uniform(0.0, 0.4, size=(T, C)).astype(np.float32)
+    llr = rng.normal(1.0, 1.2, size=(300, 120)).astype(np.float32)
+    check(H, llr, T, PATHS[path], alpha, beta, what="nms")
+    check(H, llr, 7, PATHS[path] | 1, alpha, beta, what="nms no-exit")
+    ones, zeros = np.ones((T, C), np.float32), np.zeros((T, C), np.float32)
+    g1 = gpu_decode(H, llr, T, PATHS[path], ones, zeros)
+    g0 = gpu_decode(H, llr, T, PATHS[path])
+    for x, y in zip(g1, g0):
+        assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("path", sorted(PATHS))
+def test_medium_code_subset(path):
+    """(3,6) n=1024 code, random codewords, 4096 frames at 1.5 dB, L = 50."""
+    H = wl.regular_ldpc(1024, 512, 3, 6, seed=2)
+    enc = wl.gf2_encoder(H)
+    cw = enc.random_codewords(4096, seed=201)
+    llr = wl.bpsk_awgn_llr(cw, 1.5, 0.5, seed=301)
+    check(H, llr, 50, PATHS[path], what="C1 subset")
+
+
+def test_determinism():
+    H = wl.regular_ldpc(1024, 512, 3, 6, seed=2)
+    llr = wl.bpsk_awgn_llr(None, 1.25, 0.5, seed=5, n=1024, batch=700)
+    a = gpu_decode(H, llr, 30)
+    b = gpu_decode(H, llr, 30)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
