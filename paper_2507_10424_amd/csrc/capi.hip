@@ -10,21 +10,32 @@ int check_common(const ldpc_graph *g, const float *llr, int32_t B, int32_t L, ui
     return LDPC_OK;
 }
 
+// Path choice: forced by a flag, else on-chip whenever the graph fits.
+bool use_onchip(const ldpc_graph &g, uint32_t flags) {
+    if (flags & LDPC_FORCE_ONCHIP) return true;
+    if (flags & LDPC_FORCE_STREAM) return false;
+    return ldpc::onchip_fits(g);
+}
+
 int decode(const ldpc_graph *g, const float *llr, int32_t B, int32_t L, uint32_t flags, const float *alpha,
            const float *beta, int32_t T, uint8_t *bits, float *post, int32_t *iters, uint8_t *ok, void *ws,
            size_t ws_bytes, hipStream_t stream) {
     int st = check_common(g, llr, B, L, bits, iters);
     if (st) return st;
+    if ((flags & LDPC_FORCE_STREAM) && (flags & LDPC_FORCE_ONCHIP)) return LDPC_EINVAL;
     if (B == 0) return LDPC_OK;
-    if (flags & LDPC_FORCE_ONCHIP) return LDPC_EUNSUPPORTED;
+    if (use_onchip(*g, flags)) {
+        if (!ldpc::onchip_fits(*g)) return LDPC_EUNSUPPORTED;
+        return ldpc::onchip_decode(*g, llr, B, L, flags, alpha, beta, T, bits, post, iters, ok, ws, ws_bytes, stream);
+    }
     return ldpc::stream_decode(*g, llr, B, L, flags, alpha, beta, T, bits, post, iters, ok, ws, ws_bytes, stream);
 }
 
 } // namespace
 
 extern "C" size_t ldpc_decode_workspace_bytes(const ldpc_graph *g, int32_t B, uint32_t flags) {
-    (void)flags;
     if (!g || B <= 0) return 0;
+    if (use_onchip(*g, flags)) return ldpc::onchip_workspace_bytes(*g, B);
     return ldpc::stream_workspace_bytes(*g, B);
 }
 

@@ -96,6 +96,12 @@ __global__ void k_edge_pos(const int32_t *__restrict__ csc_edge, int64_t E, int3
     if (k < E) edge_pos[csc_edge[k]] = (int32_t)k;
 }
 
+__global__ void k_edge_tab(const int32_t *__restrict__ col_idx, const int32_t *__restrict__ edge_pos, int64_t E,
+                           uint32_t *__restrict__ tab) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < E) tab[e] = (uint32_t)col_idx[e] | ((uint32_t)edge_pos[e] << 16);
+}
+
 void free_graph_arrays(ldpc_graph *g) {
     if (!g) return;
     (void)hipFree(g->row_ptr);
@@ -104,7 +110,9 @@ void free_graph_arrays(ldpc_graph *g) {
     (void)hipFree(g->csc_edge);
     (void)hipFree(g->row_class);
     (void)hipFree(g->edge_pos);
+    (void)hipFree(g->edge_tab);
     g->row_ptr = g->col_idx = g->col_ptr = g->csc_edge = g->row_class = g->edge_pos = nullptr;
+    g->edge_tab = nullptr;
 }
 
 template <class T> hipError_t dalloc(T **p, size_t count) {
@@ -152,6 +160,7 @@ int build(const uint8_t *H, int32_t m, int32_t n, hipStream_t s, ldpc_graph *g) 
         h_rowptr[m] = (int32_t)E;
         g->E = E;
         g->dc_max = dcmax;
+        g->dc_min = *std::min_element(h_row.begin(), h_row.end());
         std::vector<int32_t> rank(n + 1, -1);
         g->class_degrees.clear();
         for (int32_t d = 1; d <= n; ++d)
@@ -196,6 +205,7 @@ int build(const uint8_t *H, int32_t m, int32_t n, hipStream_t s, ldpc_graph *g) 
         }
         h_colptr[n] = (int32_t)acc;
         g->dv_max = dvmax;
+        g->dv_min = *std::min_element(h_col.begin(), h_col.end());
         if (hipMemcpyAsync(g->col_ptr, h_colptr.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, s) !=
             hipSuccess) {
             fail(LDPC_EHIP);
@@ -205,6 +215,13 @@ int build(const uint8_t *H, int32_t m, int32_t n, hipStream_t s, ldpc_graph *g) 
             k_csc_scatter<<<eblocks, 256, 0, s>>>(g->col_idx, E, g->col_ptr, fill, g->csc_edge);
             k_csc_sort<<<(n + 255) / 256, 256, 0, s>>>(g->col_ptr, n, g->csc_edge);
             k_edge_pos<<<eblocks, 256, 0, s>>>(g->csc_edge, E, g->edge_pos);
+        }
+        if (n < 65536 && E < 65536) {
+            if (dalloc(&g->edge_tab, E) != hipSuccess) {
+                fail(LDPC_ENOMEM);
+                break;
+            }
+            if (E > 0) k_edge_tab<<<eblocks, 256, 0, s>>>(g->col_idx, g->edge_pos, E, g->edge_tab);
         }
         if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
             fail(LDPC_EHIP);
@@ -229,7 +246,9 @@ extern "C" int ldpc_build_graph(const uint8_t *H_dev, int32_t m, int32_t n, hipS
     if (!g) return LDPC_ENOMEM;
     g->m = m;
     g->n = n;
-    if (hipGetDevice(&g->device) != hipSuccess) {
+    if (hipGetDevice(&g->device) != hipSuccess ||
+        hipDeviceGetAttribute(&g->num_cu, hipDeviceAttributeMultiprocessorCount, g->device) != hipSuccess ||
+        hipDeviceGetAttribute(&g->lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, g->device) != hipSuccess) {
         delete g;
         return LDPC_EHIP;
     }

@@ -14,9 +14,12 @@
 // of its edges in ascending check index.
 struct ldpc_graph {
     int device = 0;
+    int num_cu = 0;   // compute units of the device
+    int lds_max = 0;  // LDS bytes a workgroup may allocate
     int32_t m = 0, n = 0;
     int64_t E = 0;
     int32_t dc_max = 0, dv_max = 0;
+    int32_t dc_min = 0, dv_min = 0; // smallest row / column degree (0 included)
     std::vector<int32_t> class_degrees; // distinct nonzero row degrees, ascending
     int32_t *row_ptr = nullptr;   // m + 1
     int32_t *col_idx = nullptr;   // E: bit of each edge
@@ -24,6 +27,9 @@ struct ldpc_graph {
     int32_t *csc_edge = nullptr;  // E: CSR edge number of the k-th CSC entry
     int32_t *row_class = nullptr; // m: degree class of the row (-1 for degree 0)
     int32_t *edge_pos = nullptr;  // E: CSC slot of each CSR edge (inverse of csc_edge)
+    // On-chip path tables (built when n and E are below 2^16): per CSR edge
+    // the bit index in the low 16 bits and the CSC slot in the high 16 bits.
+    uint32_t *edge_tab = nullptr; // E, or null
 };
 
 #define LDPC_HIP_TRY(expr)                                   \
@@ -38,6 +44,13 @@ constexpr int kTile = 64; // frames per tile of the streaming layout (one wavefr
 // Streaming (HBM-resident) decoder: workspace bytes and launch sequence.
 size_t stream_workspace_bytes(const ldpc_graph &g, int32_t B);
 int stream_decode(const ldpc_graph &g, const float *llr, int32_t B, int32_t L, uint32_t flags,
+                  const float *alpha, const float *beta, int32_t T, uint8_t *bits, float *post,
+                  int32_t *iters, uint8_t *ok, void *ws, size_t ws_bytes, hipStream_t stream);
+
+// On-chip (LDS-resident) decoder: whether the graph fits, workspace, launch.
+bool onchip_fits(const ldpc_graph &g);
+size_t onchip_workspace_bytes(const ldpc_graph &g, int32_t B);
+int onchip_decode(const ldpc_graph &g, const float *llr, int32_t B, int32_t L, uint32_t flags,
                   const float *alpha, const float *beta, int32_t T, uint8_t *bits, float *post,
                   int32_t *iters, uint8_t *ok, void *ws, size_t ws_bytes, hipStream_t stream);
 

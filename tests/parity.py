@@ -53,7 +53,14 @@ def assert_parity(gpu, ref, what=""):
 
 def check(H, llr, L, flags=0, alpha=None, beta=None, what=""):
     note(f"[parity] {what} m={H.shape[0]} n={H.shape[1]} B={llr.shape[0]} L={L} flags={flags}")
-    gpu = gpu_decode(H, llr, L, flags, alpha, beta)
+    from paper_2507_10424_amd import ldpc
+    try:
+        gpu = gpu_decode(H, llr, L, flags, alpha, beta)
+    except ldpc.LdpcError as e:
+        if e.status == -6 and flags & ldpc.LDPC_FORCE_ONCHIP:
+            import pytest
+            pytest.skip("graph does not fit the on-chip path")
+        raise
     ref = oracle_decode(H, llr, L, flags, alpha, beta)
     assert_parity(gpu, ref, what)
     return gpu, ref

@@ -7,7 +7,7 @@ from parity import assert_parity, check, gpu_decode, note, oracle_decode
 
 pytestmark = pytest.mark.gpu
 
-PATHS = {"stream": 2}
+PATHS = {"stream": 2, "onchip": 4}
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -135,10 +135,27 @@ def test_medium_code_subset(path):
     check(H, llr, 50, PATHS[path], what="C1 subset")
 
 
-def test_determinism():
+@pytest.mark.parametrize("path", sorted(PATHS))
+def test_determinism(path):
     H = wl.regular_ldpc(1024, 512, 3, 6, seed=2)
     llr = wl.bpsk_awgn_llr(None, 1.25, 0.5, seed=5, n=1024, batch=700)
-    a = gpu_decode(H, llr, 30)
-    b = gpu_decode(H, llr, 30)
+    a = gpu_decode(H, llr, 30, PATHS[path])
+    b = gpu_decode(H, llr, 30, PATHS[path])
     for x, y in zip(a, b):
         assert np.array_equal(x, y)
+
+
+def test_paths_agree_and_auto_choice():
+    """Both kernel paths give identical outputs; without a flag the on-chip
+    path is taken when the graph fits."""
+    from paper_2507_10424_amd import ldpc
+    import torch
+    H = wl.regular_ldpc(1024, 512, 3, 6, seed=2)
+    llr = wl.bpsk_awgn_llr(None, 1.5, 0.5, seed=8, n=1024, batch=500)
+    a = gpu_decode(H, llr, 40, ldpc.LDPC_FORCE_STREAM)
+    b = gpu_decode(H, llr, 40, ldpc.LDPC_FORCE_ONCHIP)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    g = ldpc.build_graph(torch.from_numpy(H).cuda())
+    assert ldpc.workspace_bytes(g, 500) == ldpc.workspace_bytes(g, 500, ldpc.LDPC_FORCE_ONCHIP)
+    assert ldpc.workspace_bytes(g, 500) < ldpc.workspace_bytes(g, 500, ldpc.LDPC_FORCE_STREAM)
