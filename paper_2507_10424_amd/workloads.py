@@ -97,13 +97,17 @@ def random_irregular_code(n: int, m: int, seed: int, dv_choices=(1, 2, 3, 4, 5),
         E = int(dv.sum())
         if E < min_row_degree * m:
             continue
-        # start from min degree and distribute the rest at random
-        dc = np.full(m, min_row_degree)
-        rest = E - dc.sum()
-        extra = rng.multinomial(rest, np.full(m, 1.0 / m))
-        dc = dc + extra
-        if dc.max() > min(max_row_degree, n):
+        # as equal as possible, then random unit moves between rows
+        cap = min(max_row_degree, n)
+        if E > cap * m:
             continue
+        dc = np.full(m, E // m)
+        dc[: E - dc.sum()] += 1
+        for _ in range(2 * m):
+            a, b = rng.integers(m, size=2)
+            if dc[a] > min_row_degree and dc[b] < cap:
+                dc[a] -= 1
+                dc[b] += 1
         try:
             chk, bit = _socket_graph(dv, dc, rng)
         except RuntimeError:

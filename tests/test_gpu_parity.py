@@ -72,6 +72,18 @@ def test_irregular_codes(path, seed):
 
 
 @pytest.mark.parametrize("path", sorted(PATHS))
+@pytest.mark.parametrize("shape", [(60, 24), (500, 230), (900, 420), (2000, 900), (1800, 420)])
+def test_irregular_moderate_degrees(path, shape):
+    """Irregular codes with row and column degrees <= 16 (the on-chip limits),
+    from a few rows to about a thousand."""
+    n, m = shape
+    H = wl.random_irregular_code(n, m, seed=n + m, dv_choices=(0, 1, 2, 3, 4, 5), max_row_degree=16)
+    rng = np.random.default_rng(n)
+    llr = rng.normal(1.2, 1.2, size=(333, n)).astype(np.float32)
+    check(H, llr, 30, PATHS[path], what=f"irregular moderate {shape} {path}")
+
+
+@pytest.mark.parametrize("path", sorted(PATHS))
 def test_long_rows(path):
     """Check rows of degree 30..60 (beyond a 32-bit sign mask)."""
     H = wl.random_irregular_code(300, 8, seed=9, dv_choices=(1, 2), max_row_degree=64)
