@@ -127,6 +127,40 @@ int ldpc_minsum_decode(const ldpc_graph *g, const float *llr_dev, int32_t B, int
                        uint8_t *ok_dev, void *ws_dev, size_t ws_bytes, hipStream_t stream);
 
 /*
+ * One job of a multi-code decode: a graph with its B frames and outputs,
+ * laid out as for ldpc_minsum_decode (post_dev and ok_dev may be NULL).
+ */
+typedef struct ldpc_job {
+    const ldpc_graph *g;
+    const float *llr_dev;
+    int32_t B;
+    uint8_t *bits_dev;
+    float *post_dev;
+    int32_t *iters_dev;
+    uint8_t *ok_dev;
+} ldpc_job;
+
+enum { LDPC_MAX_JOBS = 16 };
+
+/* Workspace bytes of ldpc_minsum_decode_multi for njobs jobs. */
+size_t ldpc_multi_workspace_bytes(int32_t njobs);
+
+/*
+ * Min-Sum decoding of the frames of several codes (up to LDPC_MAX_JOBS
+ * graphs, each with its own batch) in one persistent launch, with the
+ * semantics of ldpc_minsum_decode for every frame (per-frame early exit; only
+ * LDPC_NO_EARLY_EXIT is honoured among the flags).  Every graph must fit the
+ * on-chip kernel and live on the current device.  Workgroups take frames
+ * from per-job counters, largest job (frames x edges) first, and move to the
+ * next job without waiting for the others.
+ * Errors: LDPC_EINVAL (null or empty job list, null pointers in a job with
+ * B > 0, B < 0, max_iter < 0), LDPC_EUNSUPPORTED (a graph does not fit, or
+ * more than LDPC_MAX_JOBS jobs), LDPC_EWORKSPACE, LDPC_EHIP.
+ */
+int ldpc_minsum_decode_multi(const ldpc_job *jobs, int32_t njobs, int32_t max_iter, uint32_t flags, void *ws_dev,
+                             size_t ws_bytes, hipStream_t stream);
+
+/*
  * Normalised / offset Min-Sum with learned weights (an extension; the paper
  * decodes with plain Min-Sum).  Identical to ldpc_minsum_decode except that in
  * iteration t (1-based) the message magnitude mu of a check row whose degree
@@ -143,6 +177,69 @@ int ldpc_nms_decode(const ldpc_graph *g, const float *llr_dev, int32_t B, int32_
                     const float *alpha_dev, const float *beta_dev, int32_t T, uint8_t *bits_dev,
                     float *post_dev, int32_t *iters_dev, uint8_t *ok_dev, void *ws_dev, size_t ws_bytes,
                     hipStream_t stream);
+
+/*
+ * Training of the learned decoder of ldpc_nms_decode (an extension; not in
+ * the paper).  The objective unrolls exactly T iterations (no syndrome exit)
+ * and is the mean over frames and bits of
+ *     sum_{t=1..T} softplus((2 c_j - 1) s_j^(t)),
+ * the binary cross-entropy of every iteration's posterior against the
+ * transmitted bits c (P(bit = 1) = sigmoid(-s)).
+ *
+ * ldpc_nms_train_workspace_bytes: workspace for B frames, T iterations and a
+ * checkpoint of the decoder state every `ckpt_every` iterations (the
+ * forward's checkpoints stay there for the backward).
+ *
+ * ldpc_nms_train_forward: runs the T iterations with the weights (alpha_dev,
+ * beta_dev: T x n_classes float32, device), writes the mean loss to
+ * loss_dev[0] and, if post_dev is non-null, the iteration-T posteriors
+ * (B x n).  target_dev: B x n bits of the transmitted codewords, or NULL for
+ * the all-zero codeword.  The posteriors equal those of ldpc_nms_decode with
+ * LDPC_NO_EARLY_EXIT and max_iter = T, bit for bit.
+ *
+ * ldpc_nms_train_backward: gradient of grad_loss * loss with respect to alpha
+ * and beta (written to galpha_dev, gbeta_dev, T x n_classes) and, if
+ * gllr_dev is non-null, to the channel LLRs (B x n).  It reads the
+ * checkpoints of the last forward call on the same workspace and inputs and
+ * recomputes each segment of ckpt_every iterations.  The derivative of a
+ * check message's magnitude goes to the edge attaining the minimum over the
+ * row's other edges (lowest position on a tie), the sign product is held
+ * constant and the clip max(v, 0) passes the gradient where v > 0.  Sums over
+ * frames are taken in a fixed order (deterministic).
+ *
+ * Errors: LDPC_EINVAL (null pointers, B, T or ckpt_every < 1),
+ * LDPC_EWORKSPACE, LDPC_EUNSUPPORTED (more than 8 degree classes, or the
+ * per-frame state does not fit the LDS of one workgroup), LDPC_EHIP.
+ */
+size_t ldpc_nms_train_workspace_bytes(const ldpc_graph *g, int32_t B, int32_t T, int32_t ckpt_every);
+int ldpc_nms_train_forward(const ldpc_graph *g, const float *llr_dev, const uint8_t *target_dev, int32_t B,
+                           int32_t T, const float *alpha_dev, const float *beta_dev, int32_t ckpt_every,
+                           float *loss_dev, float *post_dev, void *ws_dev, size_t ws_bytes, hipStream_t stream);
+int ldpc_nms_train_backward(const ldpc_graph *g, const float *llr_dev, const uint8_t *target_dev, int32_t B,
+                            int32_t T, const float *alpha_dev, const float *beta_dev, int32_t ckpt_every,
+                            float grad_loss, float *galpha_dev, float *gbeta_dev, float *gllr_dev, void *ws_dev,
+                            size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Synthetic channel frames on the device: LLRs of BPSK over AWGN (bit c ->
+ * 1 - 2c, y = x + sigma z, LLR = 2 y / sigma^2, sigma^2 = 1 / (2 rate
+ * 10^(EbN0/10))) for the codewords cw_dev (B x n bits, NULL = all-zero), with
+ * Eb/N0 in dB drawn per frame uniformly from [ebn0_lo_db, ebn0_hi_db]
+ * (equal bounds: fixed) and written to ebn0_dev (B floats) if non-null.  The
+ * normals come from the counter-based Philox4x32-10 generator (Salmon et al.,
+ * SC 2011) keyed by `seed` and the Box-Muller transform, so a seed fixes the
+ * frames.  Errors: LDPC_EINVAL, LDPC_EHIP.
+ */
+int ldpc_awgn_llr(const uint8_t *cw_dev, int32_t B, int32_t n, float rate, float ebn0_lo_db, float ebn0_hi_db,
+                  uint64_t seed, float *llr_dev, float *ebn0_dev, hipStream_t stream);
+
+/*
+ * One Adam step (Kingma & Ba) on `count` float32 parameters in place, with
+ * first/second moment buffers m1_dev, m2_dev (zero before step 1) and the
+ * 1-based step number for the bias correction.  Errors: LDPC_EINVAL, LDPC_EHIP.
+ */
+int ldpc_adam_step(float *param_dev, const float *grad_dev, float *m1_dev, float *m2_dev, int32_t count, float lr,
+                   float beta1, float beta2, float eps, int32_t step, hipStream_t stream);
 
 /*
  * Per-kernel timing for benchmarks (decoding does not need it).

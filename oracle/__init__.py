@@ -6,4 +6,4 @@ compiled with ``-ffp-contract=off`` and no fast-math) through ctypes and shares
 nothing with the HIP library.
 """
 from .binding import (Oracle, build_oracle, load_oracle, minsum_decode, nms_decode,  # noqa: F401
-                      minsum_dense, syndrome, check_degrees)
+                      minsum_dense, syndrome, check_degrees, nms_train_loss_grad)

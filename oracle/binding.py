@@ -9,6 +9,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "minsum_oracle.c")
+SRC_GRAD = os.path.join(HERE, "nms_grad_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
 _u8p = ctypes.POINTER(ctypes.c_uint8)
@@ -22,7 +23,7 @@ def build_oracle(mutant: int = 0, out: str | None = None) -> str:
     the path of the shared library."""
     out = out or (LIB if mutant == 0 else os.path.join(HERE, f"liboracle_mutant{mutant}.so"))
     cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
-           f"-DORACLE_MUTANT={mutant}", SRC, "-o", out + ".tmp", "-lpthread", "-lm"]
+           f"-DORACLE_MUTANT={mutant}", SRC, SRC_GRAD, "-o", out + ".tmp", "-lpthread", "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(out + ".tmp", out)
     return out
@@ -47,6 +48,10 @@ class Oracle:
         lib.oracle_syndrome.restype = ctypes.c_int
         lib.oracle_check_degrees.argtypes = [_u8p, _i32, _i32, _i32p, _i32]
         lib.oracle_check_degrees.restype = _i32
+        _f64p = ctypes.POINTER(ctypes.c_double)
+        lib.oracle_nms_train_loss_grad.argtypes = [_u8p, _i32, _i32, _f64p, _u8p, _i32, _f64p, _f64p, _i32, _i32,
+                                                   _f64p, _f64p, _f64p, _f64p]
+        lib.oracle_nms_train_loss_grad.restype = ctypes.c_int
         self.lib = lib
         self.path = path
 
@@ -115,6 +120,30 @@ class Oracle:
             raise ValueError("oracle_syndrome failed")
         return out
 
+    def nms_train_loss_grad(self, H, llr, alpha, beta, targets=None, grad=True, llr_grad=False):
+        """FP64 training loss of the learned decoder (T = alpha.shape[0]
+        unrolled iterations, no early exit) and its gradient.  Returns
+        (loss, galpha, gbeta, gllr) with None for what was not asked."""
+        _f64p = ctypes.POINTER(ctypes.c_double)
+        H = np.ascontiguousarray(H, dtype=np.uint8)
+        llr = np.ascontiguousarray(np.atleast_2d(llr), dtype=np.float64)
+        alpha = np.ascontiguousarray(alpha, dtype=np.float64)
+        beta = np.ascontiguousarray(beta, dtype=np.float64)
+        T, C = alpha.shape
+        m, n = H.shape
+        B = llr.shape[0]
+        tg = None if targets is None else np.ascontiguousarray(np.atleast_2d(targets), dtype=np.uint8)
+        loss = np.zeros(1)
+        ga = np.zeros((T, C)) if grad else None
+        gb = np.zeros((T, C)) if grad else None
+        gl = np.zeros((B, n)) if (grad and llr_grad) else None
+        st = self.lib.oracle_nms_train_loss_grad(_p(H, _u8p), m, n, _p(llr, _f64p), _p(tg, _u8p), B,
+                                                 _p(alpha, _f64p), _p(beta, _f64p), T, C, _p(loss, _f64p),
+                                                 _p(ga, _f64p), _p(gb, _f64p), _p(gl, _f64p))
+        if st:
+            raise ValueError(f"oracle_nms_train_loss_grad status {st}")
+        return float(loss[0]), ga, gb, gl
+
     def check_degrees(self, H):
         H = np.ascontiguousarray(H, dtype=np.uint8)
         m, n = H.shape
@@ -131,7 +160,7 @@ _default: Oracle | None = None
 def load_oracle() -> Oracle:
     global _default
     if _default is None:
-        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < max(os.path.getmtime(SRC), os.path.getmtime(SRC_GRAD)):
             build_oracle()
         _default = Oracle(LIB)
     return _default
@@ -155,3 +184,7 @@ def syndrome(*a, **k):
 
 def check_degrees(*a, **k):
     return load_oracle().check_degrees(*a, **k)
+
+
+def nms_train_loss_grad(*a, **k):
+    return load_oracle().nms_train_loss_grad(*a, **k)

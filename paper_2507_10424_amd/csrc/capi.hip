@@ -55,6 +55,22 @@ extern "C" int ldpc_nms_decode(const ldpc_graph *g, const float *llr_dev, int32_
                   ws_dev, ws_bytes, stream);
 }
 
+extern "C" size_t ldpc_multi_workspace_bytes(int32_t njobs) { return ldpc::onchip_multi_workspace_bytes(njobs); }
+
+extern "C" int ldpc_minsum_decode_multi(const ldpc_job *jobs, int32_t njobs, int32_t max_iter, uint32_t flags,
+                                        void *ws_dev, size_t ws_bytes, hipStream_t stream) {
+    if (!jobs || njobs < 1 || max_iter < 0) return LDPC_EINVAL;
+    int device = -1;
+    for (int32_t k = 0; k < njobs; ++k) {
+        const ldpc_job &j = jobs[k];
+        if (!j.g || j.B < 0 || (j.B > 0 && (!j.llr_dev || !j.bits_dev || !j.iters_dev))) return LDPC_EINVAL;
+        if (device >= 0 && j.g->device != device) return LDPC_EINVAL;
+        device = j.g->device;
+    }
+    if (njobs > LDPC_MAX_JOBS) return LDPC_EUNSUPPORTED;
+    return ldpc::onchip_decode_multi(jobs, njobs, max_iter, flags, ws_dev, ws_bytes, stream);
+}
+
 extern "C" const char *ldpc_status_string(int status) {
     switch (status) {
     case LDPC_OK: return "ok";

@@ -35,6 +35,8 @@
 // Signs are read from sign bits: LLRs are loaded as r + 0.0f, which turns -0
 // into +0; after that no s or x can be -0, so the sign bit agrees with the
 // comparison v < 0 that defines sign() (sign(0) = +1).
+#include <algorithm>
+
 #include "ldpc_internal.h"
 
 namespace ldpc {
@@ -65,18 +67,50 @@ __device__ __forceinline__ void lds_st(unsigned char *base, uint32_t off, vf2 v)
     *reinterpret_cast<vf2 *>(base + off) = v;
 }
 
+// One decoding job: a graph, its frames and outputs.
+struct Job {
+    const int32_t *row_ptr;
+    const uint32_t *edge_tab;
+    const int32_t *col_ptr;
+    const int32_t *row_class;
+    int32_t m, n, E;
+    uint32_t sh_off; // LDS byte offset of Shared for this graph
+    const float *llr;
+    int32_t B;
+    uint8_t *bits;
+    float *post;
+    int32_t *iters;
+    uint8_t *ok;
+    const float *alpha, *beta; // learned weights (T x ncls) or null
+    int32_t ncls;
+    int32_t variant;  // index into kVariants
+    uint32_t *queue;  // frame counter, zero before the launch
+};
+
+// Decodes all frames of one job with the workgroup (see the file comment).
 // DC: row degree (RX: every row exactly DC, else at most DC); DV: column
 // degree (CX: every column exactly DV, else at most DV); RPT: rows per
-// thread; CPT: bits per thread (at most); MAXT: workgroup size limit (1024
-// threads leave 128 VGPRs per thread, 512 leave 256).
-template <int DC, bool RX, int DV, bool CX, int RPT, int CPT, int MAXT>
-__global__ __launch_bounds__(MAXT) void k_onchip(
-    const int32_t *__restrict__ row_ptr, const uint32_t *__restrict__ edge_tab, const int32_t *__restrict__ col_ptr,
-    const int32_t *__restrict__ row_class, int32_t m, int32_t n, int32_t E, uint32_t sh_off,
-    const float *__restrict__ llr, int32_t B, int32_t L, int32_t early, const float *__restrict__ alpha,
-    const float *__restrict__ beta, int32_t ncls, uint8_t *__restrict__ bits, float *__restrict__ post,
-    int32_t *__restrict__ iters, uint8_t *__restrict__ ok, uint32_t *__restrict__ queue) {
-    extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+// thread; CPT: bits per thread (at most).  Every thread of the workgroup
+// calls it; it returns once all frames of the job handed to this workgroup
+// are done.
+template <int DC, bool RX, int DV, bool CX, int RPT, int CPT>
+__device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t early, unsigned char *lds) {
+    const int32_t *__restrict__ row_ptr = J.row_ptr;
+    const uint32_t *__restrict__ edge_tab = J.edge_tab;
+    const int32_t *__restrict__ col_ptr = J.col_ptr;
+    const int32_t *__restrict__ row_class = J.row_class;
+    const int32_t m = J.m, n = J.n, E = J.E;
+    const uint32_t sh_off = J.sh_off;
+    const float *__restrict__ llr = J.llr;
+    const int32_t B = J.B;
+    uint8_t *__restrict__ bits = J.bits;
+    float *__restrict__ post = J.post;
+    int32_t *__restrict__ iters = J.iters;
+    uint8_t *__restrict__ ok = J.ok;
+    const float *__restrict__ alpha = J.alpha;
+    const float *__restrict__ beta = J.beta;
+    const int32_t ncls = J.ncls;
+    uint32_t *__restrict__ queue = J.queue;
     const uint32_t eta0 = (uint32_t)sizeof(vf2) * (uint32_t)n; // byte offset of eta
     Shared *sh = reinterpret_cast<Shared *>(lds + sh_off);
     const int tid = threadIdx.x;
@@ -161,19 +195,30 @@ __global__ __launch_bounds__(MAXT) void k_onchip(
             for (int k = 0; k < DC; ++k) sv[k] = lds_ld(lds, sa[r][k]);
 #pragma unroll
             for (int q = 0; q < kF; ++q) {
-                uint32_t syn = 0, par = 0, mn0 = 0x7f800000u, mn1 = 0x7f800000u;
-                float x[DC];
+                // RX: every edge of a real row is valid; rows past m compute
+                // garbage that only reaches the padding slot and is masked
+                // out of the syndrome.  Otherwise edges k >= d are masked.
+                uint32_t xb[DC], a[DC];
 #pragma unroll
                 for (int k = 0; k < DC; ++k) {
-                    const bool valid = RX ? rowv : (k < d);
-                    x[k] = sv[k][q] - eprev[r][k][q];
-                    const uint32_t xb = __float_as_uint(x[k]);
-                    const uint32_t a = valid ? (xb & 0x7fffffffu) : 0x7f800000u;
-                    syn ^= valid ? __float_as_uint(sv[k][q]) : 0u;
-                    par ^= valid ? xb : 0u;
-                    mn1 = min(mn1, max(mn0, a));
-                    mn0 = min(mn0, a);
+                    const bool valid = RX || k < d;
+                    xb[k] = __float_as_uint(sv[k][q] - eprev[r][k][q]);
+                    a[k] = valid ? (xb[k] & 0x7fffffffu) : 0x7f800000u;
                 }
+                uint32_t mn0 = a[0], mn1 = 0x7f800000u;
+#pragma unroll
+                for (int k = 1; k < DC; ++k) {
+                    mn1 = min(mn1, max(mn0, a[k]));
+                    mn0 = min(mn0, a[k]);
+                }
+                uint32_t par = 0, syn = 0;
+#pragma unroll
+                for (int k = 0; k < DC; ++k) {
+                    const bool valid = RX || k < d;
+                    par ^= valid ? xb[k] : 0u;
+                    syn ^= valid ? __float_as_uint(sv[k][q]) : 0u;
+                }
+                if (RX && !rowv) syn = 0u;
                 umask |= (syn >> 31) << q;
                 uint32_t b0 = mn0, b1 = mn1;
                 if (alpha != nullptr && tt[q] <= L && rowv) {
@@ -182,17 +227,17 @@ __global__ __launch_bounds__(MAXT) void k_onchip(
                     b0 = __float_as_uint(v0 > 0.0f ? v0 : 0.0f);
                     b1 = __float_as_uint(v1 > 0.0f ? v1 : 0.0f);
                 }
+                // the row's sign parity folded into both magnitudes; each edge
+                // then XORs in its own sign bit
                 const uint32_t sg = par & 0x80000000u;
+                const uint32_t b0s = b0 ^ sg, b1s = b1 ^ sg;
 #pragma unroll
-                for (int k = 0; k < DC; ++k) {
-                    const uint32_t xb = __float_as_uint(x[k]);
-                    const uint32_t mag = ((xb & 0x7fffffffu) == mn0) ? b1 : b0;
-                    eprev[r][k][q] = __uint_as_float(mag | ((xb ^ sg) & 0x80000000u));
-                }
+                for (int k = 0; k < DC; ++k)
+                    eprev[r][k][q] = __uint_as_float(((a[k] == mn0) ? b1s : b0s) ^ (xb[k] & 0x80000000u));
             }
 #pragma unroll
             for (int k = 0; k < DC; ++k)
-                if (RX ? rowv : (k < d)) lds_st(lds, ea[r][k], eprev[r][k]);
+                if (RX || k < d) lds_st(lds, ea[r][k], eprev[r][k]); // rows past m write the padding slot
         }
 
         // ---- per-slot syndrome over the workgroup ------------------------------
@@ -270,7 +315,7 @@ __global__ __launch_bounds__(MAXT) void k_onchip(
     }
 }
 
-using KernelFn = decltype(&k_onchip<6, true, 3, true, 2, 4, 512>);
+constexpr int kMaxThreads = 512;
 
 struct Variant {
     int dc;
@@ -279,19 +324,59 @@ struct Variant {
     bool cx;
     int rpt;
     int cpt;
-    int max_threads;
-    KernelFn fn;
 };
 
-#define V(DC, RX, DV, CX, RPT, CPT, MAXT) \
-    Variant{DC, RX, DV, CX, RPT, CPT, MAXT, &k_onchip<DC, RX, DV, CX, RPT, CPT, MAXT>}
 // Exact-degree variants for the regular codes in use first, then masked ones.
-const Variant kVariants[] = {
-    V(6, true, 3, true, 2, 4, 512),    V(6, true, 8, false, 2, 4, 512),   V(9, true, 8, false, 1, 4, 1024),
-    V(12, true, 8, false, 1, 4, 512),  V(16, true, 8, false, 1, 8, 512),  V(8, false, 8, false, 2, 4, 512),
-    V(16, false, 16, false, 1, 8, 512),
+// The order is the dispatch order of run_variant below.
+constexpr Variant kVariants[] = {
+    {6, true, 3, true, 2, 4},  {6, true, 8, false, 2, 4},  {9, true, 8, false, 2, 4},  {12, true, 8, false, 1, 4},
+    {16, true, 8, false, 1, 8}, {8, false, 8, false, 2, 4}, {16, false, 16, false, 1, 8},
 };
-#undef V
+constexpr int kNumVariants = (int)(sizeof(kVariants) / sizeof(kVariants[0]));
+
+template <int V> __device__ __forceinline__ void run_v(const Job &J, int32_t L, int32_t early, unsigned char *lds) {
+    constexpr Variant v = kVariants[V];
+    run_onchip<v.dc, v.rx, v.dv, v.cx, v.rpt, v.cpt>(J, L, early, lds);
+}
+
+__device__ __forceinline__ void run_variant(const Job &J, int32_t L, int32_t early, unsigned char *lds) {
+    switch (J.variant) {
+    case 0: run_v<0>(J, L, early, lds); break;
+    case 1: run_v<1>(J, L, early, lds); break;
+    case 2: run_v<2>(J, L, early, lds); break;
+    case 3: run_v<3>(J, L, early, lds); break;
+    case 4: run_v<4>(J, L, early, lds); break;
+    case 5: run_v<5>(J, L, early, lds); break;
+    default: run_v<6>(J, L, early, lds); break;
+    }
+}
+static_assert(kNumVariants == 7, "run_variant dispatches seven variants");
+
+// One graph per launch, one variant instantiated.
+template <int V> __global__ __launch_bounds__(kMaxThreads) void k_onchip(const Job J, int32_t L, int32_t early) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+    run_v<V>(J, L, early, lds);
+}
+
+// Several graphs in one launch: every workgroup works through the jobs in
+// order, each until that job's frame counter is exhausted (no grid-wide
+// barrier: a workgroup moves on while others finish their last frames).
+constexpr int kMaxJobs = 16;
+struct JobTable {
+    int32_t njobs;
+    Job job[kMaxJobs];
+};
+__global__ __launch_bounds__(kMaxThreads) void k_onchip_multi(const JobTable jt, int32_t L, int32_t early) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+    for (int32_t c = 0; c < jt.njobs; ++c) {
+        run_variant(jt.job[c], L, early, lds);
+        __syncthreads();
+    }
+}
+
+using KernelFn = void (*)(const Job, int32_t, int32_t);
+const KernelFn kKernels[] = {&k_onchip<0>, &k_onchip<1>, &k_onchip<2>, &k_onchip<3>,
+                             &k_onchip<4>, &k_onchip<5>, &k_onchip<6>};
 
 // Threads: whole wavefronts, enough for RPT rows and CPT bits per thread.
 int threads_for(const ldpc_graph &g, const Variant &v) {
@@ -301,19 +386,64 @@ int threads_for(const ldpc_graph &g, const Variant &v) {
     return t < 64 ? 64 : t;
 }
 
-const Variant *pick(const ldpc_graph &g) {
-    for (const Variant &v : kVariants) {
+int pick(const ldpc_graph &g) {
+    for (int k = 0; k < kNumVariants; ++k) {
+        const Variant &v = kVariants[k];
         const bool rows_ok = v.rx ? (g.dc_min == v.dc && g.dc_max == v.dc) : g.dc_max <= v.dc;
         const bool cols_ok = v.cx ? (g.dv_min == v.dv && g.dv_max == v.dv) : g.dv_max <= v.dv;
-        if (rows_ok && cols_ok && threads_for(g, v) <= v.max_threads) return &v;
+        if (rows_ok && cols_ok && threads_for(g, v) <= kMaxThreads) return k;
     }
-    return nullptr;
+    return -1;
+}
+
+Job make_job(const ldpc_graph &g, int variant, const float *llr, int32_t B, uint8_t *bits, float *post,
+             int32_t *iters, uint8_t *ok, const float *alpha, const float *beta, uint32_t *queue) {
+    Job J;
+    J.row_ptr = g.row_ptr;
+    J.edge_tab = g.edge_tab;
+    J.col_ptr = g.col_ptr;
+    J.row_class = g.row_class;
+    J.m = g.m;
+    J.n = g.n;
+    J.E = (int32_t)g.E;
+    J.sh_off = (uint32_t)state_bytes(g);
+    J.llr = llr;
+    J.B = B;
+    J.bits = bits;
+    J.post = post;
+    J.iters = iters;
+    J.ok = ok;
+    J.alpha = alpha;
+    J.beta = beta;
+    J.ncls = (int32_t)g.class_degrees.size();
+    J.variant = variant;
+    J.queue = queue;
+    return J;
+}
+
+__global__ void k_zero_words(uint32_t *p, int32_t count) {
+    const int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < count) p[k] = 0u;
+}
+
+// Grid of a persistent launch: every CU filled to its occupancy, but no more
+// workgroups than there are groups of 2 * kF frames.
+int launch_grid(const void *fn, int threads, size_t lds, int num_cu, int64_t frames, int *grid) {
+    if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) return LDPC_EHIP;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds) != hipSuccess) return LDPC_EHIP;
+    per_cu = per_cu < 1 ? 1 : per_cu;
+    const int64_t groups = (frames + 2 * kF - 1) / (2 * kF);
+    const int64_t want = (int64_t)num_cu * per_cu;
+    *grid = (int)(want < groups ? want : groups);
+    if (*grid < 1) *grid = 1;
+    return LDPC_OK;
 }
 
 } // namespace
 
 bool onchip_fits(const ldpc_graph &g) {
-    return g.edge_tab != nullptr && pick(g) != nullptr && onchip_lds_bytes(g) + 1024 <= (size_t)g.lds_max;
+    return g.edge_tab != nullptr && pick(g) >= 0 && onchip_lds_bytes(g) + 1024 <= (size_t)g.lds_max;
 }
 
 size_t onchip_workspace_bytes(const ldpc_graph &g, int32_t B) {
@@ -328,28 +458,60 @@ int onchip_decode(const ldpc_graph &g, const float *llr, int32_t B, int32_t L, u
     (void)T;
     if (!onchip_fits(g)) return LDPC_EUNSUPPORTED;
     if (ws == nullptr || ws_bytes < onchip_workspace_bytes(g, B)) return LDPC_EWORKSPACE;
-    const Variant &var = *pick(g);
-    KernelFn fn = var.fn;
-    const int threads = threads_for(g, var);
+    const int v = pick(g);
+    const KernelFn fn = kKernels[v];
+    const int threads = threads_for(g, kVariants[v]);
     const size_t lds = onchip_lds_bytes(g);
-    if (hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
-        return LDPC_EHIP;
-    int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)fn, threads, lds) != hipSuccess)
-        return LDPC_EHIP;
-    per_cu = per_cu < 1 ? 1 : per_cu;
-    const int64_t slot_groups = ((int64_t)B + 2 * kF - 1) / (2 * kF);
-    const int64_t want = (int64_t)g.num_cu * per_cu;
-    const int32_t grid = (int32_t)(want < slot_groups ? want : slot_groups);
+    int grid = 0;
+    int st = launch_grid((const void *)fn, threads, lds, g.num_cu, B, &grid);
+    if (st) return st;
     uint32_t *queue = (uint32_t *)ws;
     const int32_t early = (flags & LDPC_NO_EARLY_EXIT) ? 0 : 1;
-    const int32_t ncls = (int32_t)g.class_degrees.size();
-    const uint32_t sh_off = (uint32_t)state_bytes(g);
-    k_zero_u32<<<1, 1, 0, stream>>>(queue);
-    timed_launch(K_ONCHIP, stream, [&] {
-        fn<<<grid, threads, lds, stream>>>(g.row_ptr, g.edge_tab, g.col_ptr, g.row_class, g.m, g.n, (int32_t)g.E,
-                                            sh_off, llr, B, L, early, alpha, beta, ncls, bits, post, iters, ok, queue);
+    const Job J = make_job(g, v, llr, B, bits, post, iters, ok, alpha, beta, queue);
+    k_zero_words<<<1, 64, 0, stream>>>(queue, 1);
+    timed_launch(K_ONCHIP, stream, [&] { fn<<<grid, threads, lds, stream>>>(J, L, early); });
+    return hipGetLastError() == hipSuccess ? LDPC_OK : LDPC_EHIP;
+}
+
+size_t onchip_multi_workspace_bytes(int32_t njobs) { return align_up(4ull * (size_t)(njobs > 0 ? njobs : 1), 256); }
+
+int onchip_decode_multi(const ldpc_job *jobs, int32_t njobs, int32_t L, uint32_t flags, void *ws, size_t ws_bytes,
+                        hipStream_t stream) {
+    if (njobs > kMaxJobs) return LDPC_EUNSUPPORTED;
+    if (ws == nullptr || ws_bytes < onchip_multi_workspace_bytes(njobs)) return LDPC_EWORKSPACE;
+    // largest jobs first, so the last frames of the launch come from small jobs
+    std::vector<int32_t> order(njobs);
+    for (int32_t k = 0; k < njobs; ++k) order[k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+        return (int64_t)jobs[a].B * jobs[a].g->E > (int64_t)jobs[b].B * jobs[b].g->E;
     });
+    JobTable jt{};
+    int threads = 64;
+    size_t lds = 0;
+    int64_t frames = 0;
+    int num_cu = 0;
+    uint32_t *queues = (uint32_t *)ws;
+    for (int32_t k = 0; k < njobs; ++k) {
+        const ldpc_job &jb = jobs[order[k]];
+        const ldpc_graph &g = *jb.g;
+        if (!onchip_fits(g)) return LDPC_EUNSUPPORTED;
+        const int v = pick(g);
+        const int t = threads_for(g, kVariants[v]);
+        threads = t > threads ? t : threads;
+        lds = onchip_lds_bytes(g) > lds ? onchip_lds_bytes(g) : lds;
+        frames += jb.B;
+        num_cu = g.num_cu;
+        jt.job[k] = make_job(g, v, jb.llr_dev, jb.B, jb.bits_dev, jb.post_dev, jb.iters_dev, jb.ok_dev, nullptr,
+                             nullptr, queues + k);
+    }
+    jt.njobs = njobs;
+    if (frames == 0) return LDPC_OK;
+    int grid = 0;
+    int st = launch_grid((const void *)k_onchip_multi, threads, lds, num_cu, frames, &grid);
+    if (st) return st;
+    const int32_t early = (flags & LDPC_NO_EARLY_EXIT) ? 0 : 1;
+    k_zero_words<<<1, 64, 0, stream>>>(queues, njobs);
+    timed_launch(K_ONCHIP, stream, [&] { k_onchip_multi<<<grid, threads, lds, stream>>>(jt, L, early); });
     return hipGetLastError() == hipSuccess ? LDPC_OK : LDPC_EHIP;
 }
 

@@ -96,10 +96,61 @@ __global__ void k_edge_pos(const int32_t *__restrict__ csc_edge, int64_t E, int3
     if (k < E) edge_pos[csc_edge[k]] = (int32_t)k;
 }
 
-__global__ void k_edge_tab(const int32_t *__restrict__ col_idx, const int32_t *__restrict__ edge_pos, int64_t E,
-                           uint32_t *__restrict__ tab) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e < E) tab[e] = (uint32_t)col_idx[e] | ((uint32_t)edge_pos[e] << 16);
+// Order of each row's edges in the on-chip table.  The on-chip decoder reads
+// s[bit] and writes eta[slot] for edge k of 64 consecutive rows in one
+// wavefront instruction, as 8-byte LDS accesses (two frames).  The results do
+// not depend on the order of a row's edges, so it is chosen here to spread
+// each instruction's accesses over the LDS banks.  For every block of 32
+// consecutive rows, with h_k(b) the number of rows whose k-th edge has its
+// bit (or its slot) in bank pair b (8-byte words modulo 32), a local search
+// swaps edges within rows while that lowers sum_k sum_b h_k(b)^2.
+std::vector<uint32_t> bank_balanced_edge_tab(const std::vector<int32_t> &rowptr, const std::vector<int32_t> &col,
+                                             const std::vector<int32_t> &pos, int32_t m) {
+    constexpr int kPairs = 32, kGroup = 32, kPasses = 8;
+    std::vector<int32_t> order(col.size()); // CSR edge placed at each table position
+    for (size_t e = 0; e < order.size(); ++e) order[e] = (int32_t)e;
+    for (int32_t g0 = 0; g0 < m; g0 += kGroup) {
+        const int32_t g1 = std::min<int32_t>(m, g0 + kGroup);
+        int32_t dmax = 0;
+        for (int32_t i = g0; i < g1; ++i) dmax = std::max(dmax, rowptr[i + 1] - rowptr[i]);
+        std::vector<int32_t> hs((size_t)dmax * kPairs, 0), he((size_t)dmax * kPairs, 0);
+        for (int32_t i = g0; i < g1; ++i)
+            for (int32_t k = 0; k < rowptr[i + 1] - rowptr[i]; ++k) {
+                const int32_t e = order[rowptr[i] + k];
+                ++hs[(size_t)k * kPairs + col[e] % kPairs];
+                ++he[(size_t)k * kPairs + pos[e] % kPairs];
+            }
+        // change of sum of squares when one unit moves from bin x to bin y at
+        // step k1 and one from y to x at step k2
+        auto delta = [&](std::vector<int32_t> &h, int k1, int k2, int x, int y) {
+            if (x == y) return 0;
+            const int32_t *a = &h[(size_t)k1 * kPairs], *b = &h[(size_t)k2 * kPairs];
+            return 2 * (b[x] - a[x] + a[y] - b[y]) + 4;
+        };
+        for (int pass = 0; pass < kPasses; ++pass) {
+            bool improved = false;
+            for (int32_t i = g0; i < g1; ++i) {
+                const int32_t d = rowptr[i + 1] - rowptr[i];
+                for (int k1 = 0; k1 < d; ++k1)
+                    for (int k2 = k1 + 1; k2 < d; ++k2) {
+                        int32_t &e1 = order[rowptr[i] + k1], &e2 = order[rowptr[i] + k2];
+                        const int s1 = col[e1] % kPairs, s2 = col[e2] % kPairs;
+                        const int p1 = pos[e1] % kPairs, p2 = pos[e2] % kPairs;
+                        if (delta(hs, k1, k2, s1, s2) + delta(he, k1, k2, p1, p2) >= 0) continue;
+                        --hs[(size_t)k1 * kPairs + s1]; ++hs[(size_t)k1 * kPairs + s2];
+                        --hs[(size_t)k2 * kPairs + s2]; ++hs[(size_t)k2 * kPairs + s1];
+                        --he[(size_t)k1 * kPairs + p1]; ++he[(size_t)k1 * kPairs + p2];
+                        --he[(size_t)k2 * kPairs + p2]; ++he[(size_t)k2 * kPairs + p1];
+                        std::swap(e1, e2);
+                        improved = true;
+                    }
+            }
+            if (!improved) break;
+        }
+    }
+    std::vector<uint32_t> tab(col.size());
+    for (size_t t = 0; t < tab.size(); ++t) tab[t] = (uint32_t)col[order[t]] | ((uint32_t)pos[order[t]] << 16);
+    return tab;
 }
 
 void free_graph_arrays(ldpc_graph *g) {
@@ -216,16 +267,27 @@ int build(const uint8_t *H, int32_t m, int32_t n, hipStream_t s, ldpc_graph *g) 
             k_csc_sort<<<(n + 255) / 256, 256, 0, s>>>(g->col_ptr, n, g->csc_edge);
             k_edge_pos<<<eblocks, 256, 0, s>>>(g->csc_edge, E, g->edge_pos);
         }
+        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+            fail(LDPC_EHIP);
+            break;
+        }
         if (n < 65536 && E < 65536) {
+            std::vector<int32_t> h_bit(E), h_pos(E);
+            if (E > 0 &&
+                (hipMemcpy(h_bit.data(), g->col_idx, sizeof(int32_t) * E, hipMemcpyDeviceToHost) != hipSuccess ||
+                 hipMemcpy(h_pos.data(), g->edge_pos, sizeof(int32_t) * E, hipMemcpyDeviceToHost) != hipSuccess)) {
+                fail(LDPC_EHIP);
+                break;
+            }
+            const std::vector<uint32_t> tab = bank_balanced_edge_tab(h_rowptr, h_bit, h_pos, m);
             if (dalloc(&g->edge_tab, E) != hipSuccess) {
                 fail(LDPC_ENOMEM);
                 break;
             }
-            if (E > 0) k_edge_tab<<<eblocks, 256, 0, s>>>(g->col_idx, g->edge_pos, E, g->edge_tab);
-        }
-        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
-            fail(LDPC_EHIP);
-            break;
+            if (E > 0 && hipMemcpy(g->edge_tab, tab.data(), sizeof(uint32_t) * E, hipMemcpyHostToDevice) != hipSuccess) {
+                fail(LDPC_EHIP);
+                break;
+            }
         }
     } while (false);
     (void)hipFree(row_deg);

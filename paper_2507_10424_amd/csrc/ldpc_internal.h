@@ -54,6 +54,11 @@ int onchip_decode(const ldpc_graph &g, const float *llr, int32_t B, int32_t L, u
                   const float *alpha, const float *beta, int32_t T, uint8_t *bits, float *post,
                   int32_t *iters, uint8_t *ok, void *ws, size_t ws_bytes, hipStream_t stream);
 
+// Several graphs in one on-chip launch.
+size_t onchip_multi_workspace_bytes(int32_t njobs);
+int onchip_decode_multi(const ldpc_job *jobs, int32_t njobs, int32_t L, uint32_t flags, void *ws, size_t ws_bytes,
+                        hipStream_t stream);
+
 // Kernel ids of the optional per-kernel timing (ldpc_timing_read).
 enum KernelId { K_CHECK = 0, K_BIT = 1, K_ONCHIP = 2, K_COUNT = 3 };
 bool timing_on();

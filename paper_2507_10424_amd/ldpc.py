@@ -34,6 +34,13 @@ _i64p = ctypes.POINTER(ctypes.c_int64)
 _lib = None
 
 
+class LdpcJob(ctypes.Structure):
+    """struct ldpc_job of include/ldpc.h"""
+    _fields_ = [("g", ctypes.c_void_p), ("llr_dev", ctypes.c_void_p), ("B", ctypes.c_int32),
+                ("bits_dev", ctypes.c_void_p), ("post_dev", ctypes.c_void_p), ("iters_dev", ctypes.c_void_p),
+                ("ok_dev", ctypes.c_void_p)]
+
+
 class LdpcError(RuntimeError):
     def __init__(self, status: int, what: str):
         self.status = status
@@ -63,10 +70,31 @@ def load_library():
     lib.ldpc_minsum_decode.restype = ctypes.c_int
     lib.ldpc_status_string.argtypes = [ctypes.c_int]
     lib.ldpc_status_string.restype = ctypes.c_char_p
-    if hasattr(lib, "ldpc_nms_decode"):
-        lib.ldpc_nms_decode.argtypes = [_vp, _vp, _i32, _i32, _u32, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp,
-                                        ctypes.c_size_t, _vp]
-        lib.ldpc_nms_decode.restype = ctypes.c_int
+    lib.ldpc_nms_decode.argtypes = [_vp, _vp, _i32, _i32, _u32, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp,
+                                    ctypes.c_size_t, _vp]
+    lib.ldpc_nms_decode.restype = ctypes.c_int
+    lib.ldpc_nms_train_workspace_bytes.argtypes = [_vp, _i32, _i32, _i32]
+    lib.ldpc_nms_train_workspace_bytes.restype = ctypes.c_size_t
+    lib.ldpc_nms_train_forward.argtypes = [_vp, _vp, _vp, _i32, _i32, _vp, _vp, _i32, _vp, _vp, _vp,
+                                           ctypes.c_size_t, _vp]
+    lib.ldpc_nms_train_forward.restype = ctypes.c_int
+    lib.ldpc_nms_train_backward.argtypes = [_vp, _vp, _vp, _i32, _i32, _vp, _vp, _i32, ctypes.c_float, _vp, _vp,
+                                            _vp, _vp, ctypes.c_size_t, _vp]
+    lib.ldpc_nms_train_backward.restype = ctypes.c_int
+    lib.ldpc_awgn_llr.argtypes = [_vp, _i32, _i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                  ctypes.c_uint64, _vp, _vp, _vp]
+    lib.ldpc_awgn_llr.restype = ctypes.c_int
+    lib.ldpc_adam_step.argtypes = [_vp, _vp, _vp, _vp, _i32, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                   ctypes.c_float, _i32, _vp]
+    lib.ldpc_adam_step.restype = ctypes.c_int
+    lib.ldpc_multi_workspace_bytes.argtypes = [_i32]
+    lib.ldpc_multi_workspace_bytes.restype = ctypes.c_size_t
+    lib.ldpc_minsum_decode_multi.argtypes = [ctypes.POINTER(LdpcJob), _i32, _i32, _u32, _vp, ctypes.c_size_t, _vp]
+    lib.ldpc_minsum_decode_multi.restype = ctypes.c_int
+    lib.ldpc_timing_enable.argtypes = [ctypes.c_int]
+    lib.ldpc_timing_enable.restype = ctypes.c_int
+    lib.ldpc_timing_read.argtypes = [_i32, ctypes.POINTER(ctypes.c_double), _i64p]
+    lib.ldpc_timing_read.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -173,8 +201,6 @@ def nms_decode(g: Graph, llr: torch.Tensor, max_iter: int, alpha: torch.Tensor, 
     per-check-degree weights alpha, beta of shape (T, n_classes), float32,
     on the GPU."""
     lib = load_library()
-    if not hasattr(lib, "ldpc_nms_decode"):
-        raise RuntimeError("libldpc.so has no ldpc_nms_decode")
     llr = _check_llr(g, llr)
     B = llr.shape[0]
     T = alpha.shape[0]
@@ -193,3 +219,116 @@ def nms_decode(g: Graph, llr: torch.Tensor, max_iter: int, alpha: torch.Tensor, 
     if st:
         raise LdpcError(st, "ldpc_nms_decode")
     return bits, post, iters, ok
+
+
+# ---------------------------------------------------------------------------
+# training of the learned decoder, synthetic frames, Adam
+# ---------------------------------------------------------------------------
+
+def train_workspace_bytes(g: Graph, B: int, T: int, ckpt_every: int) -> int:
+    return int(load_library().ldpc_nms_train_workspace_bytes(g.handle, int(B), int(T), int(ckpt_every)))
+
+
+def _check_weights(g: Graph, alpha: torch.Tensor, beta: torch.Tensor):
+    T = alpha.shape[0]
+    if alpha.shape != (T, len(g.check_degrees)) or beta.shape != alpha.shape:
+        raise ValueError("alpha and beta must be (T, n_classes)")
+    if alpha.dtype != torch.float32 or beta.dtype != torch.float32 or not alpha.is_cuda or not beta.is_cuda:
+        raise ValueError("alpha and beta must be float32 CUDA tensors")
+    return alpha.contiguous(), beta.contiguous(), T
+
+
+def nms_train_forward(g: Graph, llr: torch.Tensor, alpha: torch.Tensor, beta: torch.Tensor, ckpt_every: int,
+                      workspace: torch.Tensor, target: torch.Tensor | None = None, want_post: bool = False):
+    """ldpc_nms_train_forward: returns (loss (1,) float32 tensor, post or None)."""
+    llr = _check_llr(g, llr)
+    alpha, beta, T = _check_weights(g, alpha, beta)
+    B = llr.shape[0]
+    loss = torch.empty(1, dtype=torch.float32, device=llr.device)
+    post = torch.empty((B, g.n), dtype=torch.float32, device=llr.device) if want_post else None
+    tg = None if target is None else target.to(torch.uint8).contiguous()
+    with torch.cuda.device(llr.device):
+        st = load_library().ldpc_nms_train_forward(g.handle, _ptr(llr), _ptr(tg), B, T, _ptr(alpha), _ptr(beta),
+                                                   int(ckpt_every), _ptr(loss), _ptr(post), _ptr(workspace),
+                                                   workspace.numel(), _stream(llr.device))
+    if st:
+        raise LdpcError(st, "ldpc_nms_train_forward")
+    return loss, post
+
+
+def nms_train_backward(g: Graph, llr: torch.Tensor, alpha: torch.Tensor, beta: torch.Tensor, ckpt_every: int,
+                       workspace: torch.Tensor, grad_loss: float = 1.0, target: torch.Tensor | None = None,
+                       want_llr_grad: bool = False):
+    """ldpc_nms_train_backward: returns (galpha, gbeta, gllr or None)."""
+    llr = _check_llr(g, llr)
+    alpha, beta, T = _check_weights(g, alpha, beta)
+    B = llr.shape[0]
+    ga = torch.empty_like(alpha)
+    gb = torch.empty_like(beta)
+    gl = torch.empty_like(llr) if want_llr_grad else None
+    tg = None if target is None else target.to(torch.uint8).contiguous()
+    with torch.cuda.device(llr.device):
+        st = load_library().ldpc_nms_train_backward(g.handle, _ptr(llr), _ptr(tg), B, T, _ptr(alpha), _ptr(beta),
+                                                    int(ckpt_every), float(grad_loss), _ptr(ga), _ptr(gb), _ptr(gl),
+                                                    _ptr(workspace), workspace.numel(), _stream(llr.device))
+    if st:
+        raise LdpcError(st, "ldpc_nms_train_backward")
+    return ga, gb, gl
+
+
+def awgn_llr(B: int, n: int, rate: float, ebn0_db, seed: int, device, codewords: torch.Tensor | None = None,
+             want_ebn0: bool = False):
+    """ldpc_awgn_llr: (B, n) float32 LLRs of BPSK over AWGN generated on the
+    GPU; ebn0_db is a value or a (lo, hi) range drawn per frame."""
+    lo, hi = (float(ebn0_db), float(ebn0_db)) if not isinstance(ebn0_db, (tuple, list)) else map(float, ebn0_db)
+    llr = torch.empty((B, n), dtype=torch.float32, device=device)
+    eb = torch.empty((B,), dtype=torch.float32, device=device) if want_ebn0 else None
+    cw = None if codewords is None else codewords.to(torch.uint8).contiguous()
+    with torch.cuda.device(llr.device):
+        st = load_library().ldpc_awgn_llr(_ptr(cw), int(B), int(n), float(rate), lo, hi,
+                                          ctypes.c_uint64(int(seed) & ((1 << 64) - 1)), _ptr(llr), _ptr(eb),
+                                          _stream(llr.device))
+    if st:
+        raise LdpcError(st, "ldpc_awgn_llr")
+    return (llr, eb) if want_ebn0 else llr
+
+
+def adam_step(param: torch.Tensor, grad: torch.Tensor, m1: torch.Tensor, m2: torch.Tensor, lr: float, step: int,
+              betas=(0.9, 0.999), eps: float = 1e-8):
+    """ldpc_adam_step on contiguous float32 CUDA tensors, in place."""
+    for t in (param, grad, m1, m2):
+        if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous():
+            raise ValueError("adam_step needs contiguous float32 CUDA tensors")
+    with torch.cuda.device(param.device):
+        st = load_library().ldpc_adam_step(_ptr(param), _ptr(grad), _ptr(m1), _ptr(m2), param.numel(), float(lr),
+                                           float(betas[0]), float(betas[1]), float(eps), int(step),
+                                           _stream(param.device))
+    if st:
+        raise LdpcError(st, "ldpc_adam_step")
+
+
+def minsum_decode_multi(jobs, max_iter: int, flags: int = 0, want_post: bool = True, workspace=None, outs=None):
+    """ldpc_minsum_decode_multi: jobs is a list of (Graph, llr) pairs decoded
+    in one launch.  Returns a list of (bits, post, iters, ok), one per job."""
+    if not jobs:
+        raise ValueError("no jobs")
+    lib = load_library()
+    arr = (LdpcJob * len(jobs))()
+    results = []
+    for k, (g, llr) in enumerate(jobs):
+        llr = _check_llr(g, llr)
+        o = outs[k] if outs is not None else _outputs(llr.shape[0], g.n, llr.device, want_post)
+        results.append((llr, o))
+        bits, post, iters, ok = o
+        arr[k] = LdpcJob(g.handle.value, llr.data_ptr(), llr.shape[0], bits.data_ptr(),
+                         post.data_ptr() if post is not None else None, iters.data_ptr(), ok.data_ptr())
+    dev = jobs[0][1].device
+    need = int(lib.ldpc_multi_workspace_bytes(len(jobs)))
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=dev)
+    with torch.cuda.device(dev):
+        st = lib.ldpc_minsum_decode_multi(arr, len(jobs), int(max_iter), int(flags), _ptr(workspace),
+                                          workspace.numel(), _stream(dev))
+    if st:
+        raise LdpcError(st, "ldpc_minsum_decode_multi")
+    return [o for _, o in results]

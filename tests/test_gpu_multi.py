@@ -1,0 +1,60 @@
+"""Several codes decoded in one persistent launch (GPU): per-code parity with
+the oracle and equality with one launch per code."""
+import numpy as np
+import pytest
+
+from paper_2507_10424_amd import workloads as wl
+from parity import assert_parity, note, oracle_decode
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tdev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch, torch.device("cuda:0")
+
+
+def test_eight_qc_codes_one_launch(tdev):
+    torch, dev = tdev
+    from paper_2507_10424_amd import ldpc
+    fam = wl.qc_multi_code_family(seed=7)
+    jobs, inputs = [], []
+    for k, c in enumerate(fam):
+        B = 96 + 37 * k  # uneven batches
+        llr = wl.bpsk_awgn_llr(None, 2.0, c["rate"], seed=600 + k, n=c["n"], batch=B)
+        g = ldpc.build_graph(torch.from_numpy(c["H"]).to(dev))
+        jobs.append((g, torch.from_numpy(llr).to(dev)))
+        inputs.append((c["H"], llr))
+    outs = ldpc.minsum_decode_multi(jobs, 50)
+    torch.cuda.synchronize()
+    for k, ((H, llr), o, (g, lt)) in enumerate(zip(inputs, outs, jobs)):
+        got = tuple(t.cpu().numpy() for t in o)
+        note(f"[multi] code {k}: n={H.shape[1]} m={H.shape[0]} B={llr.shape[0]} mean iters {got[2].mean():.2f}")
+        assert_parity(got, oracle_decode(H, llr, 50), f"multi code {k}")
+        single = ldpc.minsum_decode(g, lt, 50)
+        torch.cuda.synchronize()
+        for x, y in zip(o, single):
+            assert torch.equal(x, y)
+
+
+def test_multi_mixed_sizes_and_empty_job(tdev):
+    torch, dev = tdev
+    from paper_2507_10424_amd import ldpc
+    codes = [wl.regular_ldpc(96, 48, 3, 6, seed=1), wl.regular_ldpc(1024, 512, 3, 6, seed=2),
+             wl.random_irregular_code(300, 120, seed=3, dv_choices=(1, 2, 3, 4), max_row_degree=8)]
+    Bs = [500, 0, 130]
+    jobs, inputs = [], []
+    for k, (H, B) in enumerate(zip(codes, Bs)):
+        llr = np.random.default_rng(k).normal(1.1, 1.2, size=(B, H.shape[1])).astype(np.float32)
+        g = ldpc.build_graph(torch.from_numpy(H).to(dev))
+        jobs.append((g, torch.from_numpy(llr).to(dev)))
+        inputs.append((H, llr))
+    outs = ldpc.minsum_decode_multi(jobs, 30)
+    torch.cuda.synchronize()
+    for k, ((H, llr), o) in enumerate(zip(inputs, outs)):
+        if llr.shape[0] == 0:
+            continue
+        assert_parity(tuple(t.cpu().numpy() for t in o), oracle_decode(H, llr, 30), f"mixed {k}")
