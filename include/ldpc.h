@@ -32,7 +32,7 @@
 extern "C" {
 #endif
 
-typedef struct ldpc_graph ldpc_graph; /* opaque; immutable once built */
+typedef struct ldpc_graph ldpc_graph; /* opaque; immutable once built, except its tuning record */
 
 enum ldpc_status {
     LDPC_OK = 0,
@@ -240,6 +240,48 @@ int ldpc_awgn_llr(const uint8_t *cw_dev, int32_t B, int32_t n, float rate, float
  */
 int ldpc_adam_step(float *param_dev, const float *grad_dev, float *m1_dev, float *m2_dev, int32_t count, float lr,
                    float beta1, float beta2, float eps, int32_t step, hipStream_t stream);
+
+/*
+ * Launch choices of a graph ("tuning record").  Without one, decoding takes
+ * the on-chip path whenever the graph fits (its first fitting kernel
+ * variant, as many workgroups as fit on each CU) and otherwise the streaming
+ * path with 4 wavefronts per workgroup.
+ *   path          1 on-chip, 2 streaming (0 in ldpc_graph_get_tuning: none set)
+ *   variant       on-chip kernel variant (degree template and rows per
+ *                 thread), -1 for the first that fits
+ *   wg_per_cu     on-chip workgroups per CU, 0 for the occupancy limit
+ *   stream_waves  wavefronts per workgroup of the streaming kernels (1..8)
+ *   ms            ldpc_autotune: mean time of one decode of the tuning batch
+ * LDPC_FORCE_STREAM / LDPC_FORCE_ONCHIP still override the path.
+ */
+typedef struct ldpc_tuning {
+    int32_t path;
+    int32_t variant;
+    int32_t wg_per_cu;
+    int32_t stream_waves;
+    float ms;
+} ldpc_tuning;
+
+/* Set (t != NULL) or clear (t == NULL) the tuning record.  Not thread-safe
+ * against concurrent decodes of the same graph.  Errors: LDPC_EINVAL,
+ * LDPC_EUNSUPPORTED (the variant does not fit the graph). */
+int ldpc_graph_set_tuning(ldpc_graph *g, const ldpc_tuning *t);
+int ldpc_graph_get_tuning(const ldpc_graph *g, ldpc_tuning *t);
+
+/*
+ * Autotuner: generates B all-zero frames at ebn0_db on the device, times one
+ * warm-up and three decodes (at most max_iter iterations, early exit) for
+ * every launch choice that applies to the graph (each fitting on-chip
+ * variant with 0..4 workgroups per CU, the streaming path with 1, 2, 4, 8
+ * wavefronts per workgroup), and stores the fastest in the graph's tuning
+ * record (also returned in *best if non-null).  It synchronises `stream`
+ * and creates two HIP events; do not capture it.  The workspace needs
+ * ldpc_autotune_workspace_bytes(g, B) bytes.
+ * Errors: LDPC_EINVAL, LDPC_EWORKSPACE, LDPC_EHIP.
+ */
+size_t ldpc_autotune_workspace_bytes(const ldpc_graph *g, int32_t B);
+int ldpc_autotune(ldpc_graph *g, int32_t B, int32_t max_iter, float ebn0_db, void *ws_dev, size_t ws_bytes,
+                  hipStream_t stream, ldpc_tuning *best);
 
 /*
  * Per-kernel timing for benchmarks (decoding does not need it).

@@ -1,0 +1,159 @@
+// Autotuner: times the launch choices that apply to a graph on a batch of
+// synthetic frames and keeps the fastest in the graph's tuning record.
+//
+// Choices: the on-chip path with each kernel variant that fits the graph
+// (exact or masked degree templates, one or two rows per thread) and a cap
+// on workgroups per CU (occupancy limit, 1, 2, 3, 4); the streaming path
+// with 1, 2, 4 or 8 wavefronts per workgroup of its check and bit kernels.
+#include <vector>
+
+#include "ldpc_internal.h"
+
+namespace ldpc {
+namespace {
+
+struct AutoWs {
+    float *llr, *post;
+    uint8_t *bits, *ok;
+    int32_t *iters;
+    void *dec;
+    size_t dec_bytes;
+};
+
+size_t decode_ws_max(const ldpc_graph &g, int32_t B) {
+    size_t a = stream_workspace_bytes(g, B), b = onchip_workspace_bytes(g, B);
+    return a > b ? a : b;
+}
+
+AutoWs carve_auto(const ldpc_graph &g, int32_t B, void *base, size_t *total) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes, 256);
+        return o;
+    };
+    const size_t nb = (size_t)B * (size_t)g.n;
+    const size_t o_l = take(nb * 4), o_p = take(nb * 4), o_b = take(nb), o_o = take((size_t)B),
+                 o_i = take((size_t)B * 4);
+    const size_t dec = decode_ws_max(g, B);
+    const size_t o_d = take(dec);
+    if (total) *total = off;
+    AutoWs w{};
+    if (base) {
+        char *p = (char *)base;
+        w.llr = (float *)(p + o_l);
+        w.post = (float *)(p + o_p);
+        w.bits = (uint8_t *)(p + o_b);
+        w.ok = (uint8_t *)(p + o_o);
+        w.iters = (int32_t *)(p + o_i);
+        w.dec = p + o_d;
+        w.dec_bytes = dec;
+    }
+    return w;
+}
+
+} // namespace
+} // namespace ldpc
+
+using namespace ldpc;
+
+extern "C" int ldpc_graph_set_tuning(ldpc_graph *g, const ldpc_tuning *t) {
+    if (!g) return LDPC_EINVAL;
+    if (!t) {
+        g->tuning.set = false;
+        return LDPC_OK;
+    }
+    if (t->path != 1 && t->path != 2) return LDPC_EINVAL;
+    if (t->path == 1 && (t->variant < -1 || t->variant >= onchip_num_variants() || t->wg_per_cu < 0)) return LDPC_EINVAL;
+    if (t->path == 1 && t->variant >= 0 && !onchip_variant_fits(*g, t->variant)) return LDPC_EUNSUPPORTED;
+    if (t->path == 1 && t->variant < 0 && !onchip_fits(*g)) return LDPC_EUNSUPPORTED;
+    if (t->path == 2 && (t->stream_waves < 1 || t->stream_waves > 8)) return LDPC_EINVAL;
+    g->tuning.set = true;
+    g->tuning.path = t->path;
+    g->tuning.variant = t->variant;
+    g->tuning.wg_per_cu = t->wg_per_cu;
+    g->tuning.stream_waves = t->path == 2 ? t->stream_waves : 4;
+    return LDPC_OK;
+}
+
+extern "C" int ldpc_graph_get_tuning(const ldpc_graph *g, ldpc_tuning *t) {
+    if (!g || !t) return LDPC_EINVAL;
+    t->path = g->tuning.set ? g->tuning.path : 0;
+    t->variant = g->tuning.variant;
+    t->wg_per_cu = g->tuning.wg_per_cu;
+    t->stream_waves = g->tuning.stream_waves;
+    t->ms = 0.0f;
+    return LDPC_OK;
+}
+
+extern "C" size_t ldpc_autotune_workspace_bytes(const ldpc_graph *g, int32_t B) {
+    if (!g || B < 1) return 0;
+    size_t total = 0;
+    carve_auto(*g, B, nullptr, &total);
+    return total;
+}
+
+extern "C" int ldpc_awgn_llr(const uint8_t *cw_dev, int32_t B, int32_t n, float rate, float ebn0_lo_db,
+                             float ebn0_hi_db, uint64_t seed, float *llr_dev, float *ebn0_dev, hipStream_t stream);
+
+extern "C" int ldpc_autotune(ldpc_graph *g, int32_t B, int32_t max_iter, float ebn0_db, void *ws_dev, size_t ws_bytes,
+                             hipStream_t stream, ldpc_tuning *best) {
+    if (!g || B < 1 || max_iter < 0) return LDPC_EINVAL;
+    size_t need = 0;
+    AutoWs w = carve_auto(*g, B, ws_dev, &need);
+    if (!ws_dev || ws_bytes < need) return LDPC_EWORKSPACE;
+    float rate = 1.0f - (float)g->m / (float)g->n;
+    if (!(rate > 0.0f)) rate = 0.5f;
+    int st = ldpc_awgn_llr(nullptr, B, g->n, rate, ebn0_db, ebn0_db, 0x5eedull, w.llr, nullptr, stream);
+    if (st) return st;
+
+    std::vector<ldpc_tuning> cands;
+    for (int v = 0; v < onchip_num_variants(); ++v) {
+        if (!onchip_variant_fits(*g, v)) continue;
+        for (int wpc : {0, 1, 2, 3, 4}) cands.push_back(ldpc_tuning{1, v, wpc, 4, 0.0f});
+    }
+    for (int waves : {1, 2, 4, 8}) cands.push_back(ldpc_tuning{2, -1, 0, waves, 0.0f});
+
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return LDPC_EHIP;
+    const auto saved = g->tuning;
+    int best_k = -1;
+    float best_ms = 0.0f;
+    constexpr int kReps = 3;
+    for (size_t k = 0; k < cands.size() && st == LDPC_OK; ++k) {
+        st = ldpc_graph_set_tuning(g, &cands[k]);
+        if (st) break;
+        auto run = [&]() {
+            return cands[k].path == 1
+                       ? onchip_decode(*g, w.llr, B, max_iter, 0, nullptr, nullptr, 0, w.bits, w.post, w.iters, w.ok,
+                                       w.dec, w.dec_bytes, stream)
+                       : stream_decode(*g, w.llr, B, max_iter, 0, nullptr, nullptr, 0, w.bits, w.post, w.iters, w.ok,
+                                       w.dec, w.dec_bytes, stream);
+        };
+        st = run(); // warm-up
+        if (st) break;
+        if (hipEventRecord(e0, stream) != hipSuccess) { st = LDPC_EHIP; break; }
+        for (int r = 0; r < kReps && st == LDPC_OK; ++r) st = run();
+        if (st) break;
+        float ms = 0.0f;
+        if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+            st = LDPC_EHIP;
+            break;
+        }
+        cands[k].ms = ms / kReps;
+        if (best_k < 0 || cands[k].ms < best_ms) {
+            best_k = (int)k;
+            best_ms = cands[k].ms;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st || best_k < 0) {
+        g->tuning = saved;
+        return st ? st : LDPC_EHIP;
+    }
+    st = ldpc_graph_set_tuning(g, &cands[best_k]);
+    if (best) *best = cands[best_k];
+    return st;
+}

@@ -10,10 +10,12 @@ int check_common(const ldpc_graph *g, const float *llr, int32_t B, int32_t L, ui
     return LDPC_OK;
 }
 
-// Path choice: forced by a flag, else on-chip whenever the graph fits.
+// Path choice: forced by a flag, else the tuning record, else on-chip
+// whenever the graph fits.
 bool use_onchip(const ldpc_graph &g, uint32_t flags) {
     if (flags & LDPC_FORCE_ONCHIP) return true;
     if (flags & LDPC_FORCE_STREAM) return false;
+    if (g.tuning.set && g.tuning.path == 2) return false;
     return ldpc::onchip_fits(g);
 }
 

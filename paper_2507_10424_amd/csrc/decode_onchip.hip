@@ -329,8 +329,8 @@ struct Variant {
 // Exact-degree variants for the regular codes in use first, then masked ones.
 // The order is the dispatch order of run_variant below.
 constexpr Variant kVariants[] = {
-    {6, true, 3, true, 2, 4},  {6, true, 8, false, 2, 4},  {9, true, 8, false, 2, 4},  {12, true, 8, false, 1, 4},
-    {16, true, 8, false, 1, 8}, {8, false, 8, false, 2, 4}, {16, false, 16, false, 1, 8},
+    {6, true, 3, true, 2, 4},   {6, true, 8, false, 2, 4},  {9, true, 8, false, 2, 8},   {12, true, 8, false, 1, 4},
+    {16, true, 8, false, 1, 8}, {8, false, 8, false, 2, 4}, {16, false, 16, false, 1, 8}, {6, true, 3, true, 1, 4},
 };
 constexpr int kNumVariants = (int)(sizeof(kVariants) / sizeof(kVariants[0]));
 
@@ -347,10 +347,11 @@ __device__ __forceinline__ void run_variant(const Job &J, int32_t L, int32_t ear
     case 3: run_v<3>(J, L, early, lds); break;
     case 4: run_v<4>(J, L, early, lds); break;
     case 5: run_v<5>(J, L, early, lds); break;
-    default: run_v<6>(J, L, early, lds); break;
+    case 6: run_v<6>(J, L, early, lds); break;
+    default: run_v<7>(J, L, early, lds); break;
     }
 }
-static_assert(kNumVariants == 7, "run_variant dispatches seven variants");
+static_assert(kNumVariants == 8, "run_variant dispatches eight variants");
 
 // One graph per launch, one variant instantiated.
 template <int V> __global__ __launch_bounds__(kMaxThreads) void k_onchip(const Job J, int32_t L, int32_t early) {
@@ -376,7 +377,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_onchip_multi(const JobTable jt,
 
 using KernelFn = void (*)(const Job, int32_t, int32_t);
 const KernelFn kKernels[] = {&k_onchip<0>, &k_onchip<1>, &k_onchip<2>, &k_onchip<3>,
-                             &k_onchip<4>, &k_onchip<5>, &k_onchip<6>};
+                             &k_onchip<4>, &k_onchip<5>, &k_onchip<6>, &k_onchip<7>};
 
 // Threads: whole wavefronts, enough for RPT rows and CPT bits per thread.
 int threads_for(const ldpc_graph &g, const Variant &v) {
@@ -386,13 +387,19 @@ int threads_for(const ldpc_graph &g, const Variant &v) {
     return t < 64 ? 64 : t;
 }
 
+bool variant_ok(const ldpc_graph &g, int k) {
+    if (k < 0 || k >= kNumVariants) return false;
+    const Variant &v = kVariants[k];
+    const bool rows_ok = v.rx ? (g.dc_min == v.dc && g.dc_max == v.dc) : g.dc_max <= v.dc;
+    const bool cols_ok = v.cx ? (g.dv_min == v.dv && g.dv_max == v.dv) : g.dv_max <= v.dv;
+    return rows_ok && cols_ok && threads_for(g, v) <= kMaxThreads;
+}
+
+// The tuned variant if one is set and valid, else the first that fits.
 int pick(const ldpc_graph &g) {
-    for (int k = 0; k < kNumVariants; ++k) {
-        const Variant &v = kVariants[k];
-        const bool rows_ok = v.rx ? (g.dc_min == v.dc && g.dc_max == v.dc) : g.dc_max <= v.dc;
-        const bool cols_ok = v.cx ? (g.dv_min == v.dv && g.dv_max == v.dv) : g.dv_max <= v.dv;
-        if (rows_ok && cols_ok && threads_for(g, v) <= kMaxThreads) return k;
-    }
+    if (g.tuning.set && variant_ok(g, g.tuning.variant)) return g.tuning.variant;
+    for (int k = 0; k < kNumVariants; ++k)
+        if (variant_ok(g, k)) return k;
     return -1;
 }
 
@@ -428,10 +435,11 @@ __global__ void k_zero_words(uint32_t *p, int32_t count) {
 
 // Grid of a persistent launch: every CU filled to its occupancy, but no more
 // workgroups than there are groups of 2 * kF frames.
-int launch_grid(const void *fn, int threads, size_t lds, int num_cu, int64_t frames, int *grid) {
+int launch_grid(const void *fn, int threads, size_t lds, int num_cu, int64_t frames, int cap_per_cu, int *grid) {
     if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) return LDPC_EHIP;
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds) != hipSuccess) return LDPC_EHIP;
+    if (cap_per_cu > 0 && per_cu > cap_per_cu) per_cu = cap_per_cu;
     per_cu = per_cu < 1 ? 1 : per_cu;
     const int64_t groups = (frames + 2 * kF - 1) / (2 * kF);
     const int64_t want = (int64_t)num_cu * per_cu;
@@ -445,6 +453,12 @@ int launch_grid(const void *fn, int threads, size_t lds, int num_cu, int64_t fra
 bool onchip_fits(const ldpc_graph &g) {
     return g.edge_tab != nullptr && pick(g) >= 0 && onchip_lds_bytes(g) + 1024 <= (size_t)g.lds_max;
 }
+
+bool onchip_variant_fits(const ldpc_graph &g, int variant) {
+    return g.edge_tab != nullptr && variant_ok(g, variant) && onchip_lds_bytes(g) + 1024 <= (size_t)g.lds_max;
+}
+
+int onchip_num_variants() { return kNumVariants; }
 
 size_t onchip_workspace_bytes(const ldpc_graph &g, int32_t B) {
     (void)g;
@@ -463,7 +477,7 @@ int onchip_decode(const ldpc_graph &g, const float *llr, int32_t B, int32_t L, u
     const int threads = threads_for(g, kVariants[v]);
     const size_t lds = onchip_lds_bytes(g);
     int grid = 0;
-    int st = launch_grid((const void *)fn, threads, lds, g.num_cu, B, &grid);
+    int st = launch_grid((const void *)fn, threads, lds, g.num_cu, B, g.tuning.set ? g.tuning.wg_per_cu : 0, &grid);
     if (st) return st;
     uint32_t *queue = (uint32_t *)ws;
     const int32_t early = (flags & LDPC_NO_EARLY_EXIT) ? 0 : 1;
@@ -507,7 +521,7 @@ int onchip_decode_multi(const ldpc_job *jobs, int32_t njobs, int32_t L, uint32_t
     jt.njobs = njobs;
     if (frames == 0) return LDPC_OK;
     int grid = 0;
-    int st = launch_grid((const void *)k_onchip_multi, threads, lds, num_cu, frames, &grid);
+    int st = launch_grid((const void *)k_onchip_multi, threads, lds, num_cu, frames, 0, &grid);
     if (st) return st;
     const int32_t early = (flags & LDPC_NO_EARLY_EXIT) ? 0 : 1;
     k_zero_words<<<1, 64, 0, stream>>>(queues, njobs);

@@ -30,7 +30,7 @@
 namespace ldpc {
 namespace {
 
-constexpr int kWaves = 4; // wavefronts per workgroup
+constexpr int kWaves = 4; // wavefronts per workgroup of the transpose kernels
 
 struct StreamWs {
     float *r, *s, *eta;
@@ -105,7 +105,7 @@ __global__ __launch_bounds__(256) void k_to_tiles(const float *__restrict__ llr,
 
 // One wavefront = one check row x one frame tile.  `t` is the iteration
 // being computed (1-based).
-__global__ __launch_bounds__(256) void k_check(const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx,
+__global__ __launch_bounds__(512) void k_check(const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx,
                                                const int32_t *__restrict__ row_class, int32_t m, int32_t n, int64_t E,
                                                int32_t B, int32_t row_blocks, const float *__restrict__ r,
                                                const float *__restrict__ s, float *__restrict__ eta,
@@ -115,7 +115,7 @@ __global__ __launch_bounds__(256) void k_check(const int32_t *__restrict__ row_p
     const uint32_t bid = xcd_swizzle(blockIdx.x, gridDim.x);
     const int32_t tile = bid / row_blocks;
     const int32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int32_t row = (bid % row_blocks) * kWaves + w;
+    const int32_t row = (bid % row_blocks) * (int32_t)(blockDim.x >> 6) + w;
     const int lane = threadIdx.x & 63;
     const int32_t f = tile * kTile + lane;
     const bool act = !done[f];
@@ -169,7 +169,7 @@ __global__ __launch_bounds__(256) void k_check(const int32_t *__restrict__ row_p
 }
 
 // One wavefront = one bit column x one frame tile.
-__global__ __launch_bounds__(256) void k_bit(const int32_t *__restrict__ col_ptr, const int32_t *__restrict__ csc_edge,
+__global__ __launch_bounds__(512) void k_bit(const int32_t *__restrict__ col_ptr, const int32_t *__restrict__ csc_edge,
                                              int32_t n, int64_t E, int32_t col_blocks, const float *__restrict__ r,
                                              float *__restrict__ s, const float *__restrict__ eta,
                                              uint32_t *__restrict__ done, const uint32_t *__restrict__ unsat_cur,
@@ -179,7 +179,7 @@ __global__ __launch_bounds__(256) void k_bit(const int32_t *__restrict__ col_ptr
     const int32_t tile = bid / col_blocks;
     const int32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int32_t cb = bid % col_blocks;
-    const int32_t col = cb * kWaves + w;
+    const int32_t col = cb * (int32_t)(blockDim.x >> 6) + w;
     const int lane = threadIdx.x & 63;
     const int32_t f = tile * kTile + lane;
     bool act = !done[f];
@@ -204,14 +204,14 @@ __global__ __launch_bounds__(256) void k_bit(const int32_t *__restrict__ col_ptr
 }
 
 // Syndrome of the current decision only (after the last iteration).
-__global__ __launch_bounds__(256) void k_syndrome(const int32_t *__restrict__ row_ptr,
+__global__ __launch_bounds__(512) void k_syndrome(const int32_t *__restrict__ row_ptr,
                                                   const int32_t *__restrict__ col_idx, int32_t m, int32_t n,
                                                   int32_t row_blocks, const float *__restrict__ sv_all,
                                                   const uint32_t *__restrict__ done, uint32_t *__restrict__ unsat) {
     const uint32_t bid = xcd_swizzle(blockIdx.x, gridDim.x);
     const int32_t tile = bid / row_blocks;
     const int32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int32_t row = (bid % row_blocks) * kWaves + w;
+    const int32_t row = (bid % row_blocks) * (int32_t)(blockDim.x >> 6) + w;
     const int lane = threadIdx.x & 63;
     const int32_t f = tile * kTile + lane;
     const bool act = !done[f];
@@ -280,8 +280,10 @@ int stream_decode(const ldpc_graph &g, const float *llr, int32_t B, int32_t L, u
     const int32_t nt = (int32_t)tiles_of(B);
     const int32_t frames = nt * kTile;
     const int32_t early = (flags & LDPC_NO_EARLY_EXIT) ? 0 : 1;
-    const int32_t row_blocks = (g.m + kWaves - 1) / kWaves;
-    const int32_t col_blocks = (g.n + kWaves - 1) / kWaves;
+    // wavefronts per workgroup of the check / bit kernels (tuning record, else 4)
+    const int32_t waves = (g.tuning.set && g.tuning.stream_waves > 0) ? g.tuning.stream_waves : 4;
+    const int32_t row_blocks = (g.m + waves - 1) / waves;
+    const int32_t col_blocks = (g.n + waves - 1) / waves;
     const int32_t nchunks = (g.n + 63) / 64;
     const int32_t ncls = (int32_t)g.class_degrees.size();
 
@@ -289,18 +291,18 @@ int stream_decode(const ldpc_graph &g, const float *llr, int32_t B, int32_t L, u
     k_to_tiles<<<nt * nchunks, 256, 0, stream>>>(llr, B, g.n, w.r);
     for (int32_t t = 1; t <= L; ++t) {
         timed_launch(K_CHECK, stream, [&] {
-            k_check<<<nt * row_blocks, 256, 0, stream>>>(g.row_ptr, g.col_idx, g.row_class, g.m, g.n, g.E, B,
+            k_check<<<nt * row_blocks, 64 * waves, 0, stream>>>(g.row_ptr, g.col_idx, g.row_class, g.m, g.n, g.E, B,
                                                          row_blocks, w.r, w.s, w.eta, w.done, w.unsat[t & 1], t,
                                                          alpha, beta, ncls);
         });
         timed_launch(K_BIT, stream, [&] {
-            k_bit<<<nt * col_blocks, 256, 0, stream>>>(g.col_ptr, g.csc_edge, g.n, g.E, col_blocks, w.r, w.s, w.eta,
+            k_bit<<<nt * col_blocks, 64 * waves, 0, stream>>>(g.col_ptr, g.csc_edge, g.n, g.E, col_blocks, w.r, w.s, w.eta,
                                                        w.done, w.unsat[t & 1], w.unsat[(t + 1) & 1], w.conv, t,
                                                        early);
         });
     }
     uint32_t *unsat_final = w.unsat[(L + 1) & 1];
-    k_syndrome<<<nt * row_blocks, 256, 0, stream>>>(g.row_ptr, g.col_idx, g.m, g.n, row_blocks, L == 0 ? w.r : w.s,
+    k_syndrome<<<nt * row_blocks, 64 * waves, 0, stream>>>(g.row_ptr, g.col_idx, g.m, g.n, row_blocks, L == 0 ? w.r : w.s,
                                                     w.done, unsat_final);
     k_finalize<<<(B + 255) / 256, 256, 0, stream>>>(B, L, w.conv, unsat_final, iters, ok);
     k_from_tiles<<<nt * nchunks, 256, 0, stream>>>(w.r, w.s, w.conv, B, g.n, L, post, bits);

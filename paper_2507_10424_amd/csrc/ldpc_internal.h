@@ -30,6 +30,14 @@ struct ldpc_graph {
     // On-chip path tables (built when n and E are below 2^16): per CSR edge
     // the bit index in the low 16 bits and the CSC slot in the high 16 bits.
     uint32_t *edge_tab = nullptr; // E, or null
+    // Launch choices picked by ldpc_autotune or set by ldpc_graph_set_tuning.
+    struct {
+        bool set = false;
+        int path = 0;         // 1 on-chip, 2 streaming
+        int variant = -1;     // on-chip kernel variant
+        int wg_per_cu = 0;    // on-chip workgroups per CU (0: occupancy limit)
+        int stream_waves = 4; // wavefronts per workgroup of the streaming kernels
+    } tuning;
 };
 
 #define LDPC_HIP_TRY(expr)                                   \
@@ -49,6 +57,8 @@ int stream_decode(const ldpc_graph &g, const float *llr, int32_t B, int32_t L, u
 
 // On-chip (LDS-resident) decoder: whether the graph fits, workspace, launch.
 bool onchip_fits(const ldpc_graph &g);
+bool onchip_variant_fits(const ldpc_graph &g, int variant);
+int onchip_num_variants();
 size_t onchip_workspace_bytes(const ldpc_graph &g, int32_t B);
 int onchip_decode(const ldpc_graph &g, const float *llr, int32_t B, int32_t L, uint32_t flags,
                   const float *alpha, const float *beta, int32_t T, uint8_t *bits, float *post,

@@ -34,6 +34,15 @@ _i64p = ctypes.POINTER(ctypes.c_int64)
 _lib = None
 
 
+class LdpcTuning(ctypes.Structure):
+    """struct ldpc_tuning of include/ldpc.h"""
+    _fields_ = [("path", ctypes.c_int32), ("variant", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32),
+                ("stream_waves", ctypes.c_int32), ("ms", ctypes.c_float)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class LdpcJob(ctypes.Structure):
     """struct ldpc_job of include/ldpc.h"""
     _fields_ = [("g", ctypes.c_void_p), ("llr_dev", ctypes.c_void_p), ("B", ctypes.c_int32),
@@ -91,6 +100,15 @@ def load_library():
     lib.ldpc_multi_workspace_bytes.restype = ctypes.c_size_t
     lib.ldpc_minsum_decode_multi.argtypes = [ctypes.POINTER(LdpcJob), _i32, _i32, _u32, _vp, ctypes.c_size_t, _vp]
     lib.ldpc_minsum_decode_multi.restype = ctypes.c_int
+    lib.ldpc_graph_set_tuning.argtypes = [_vp, ctypes.POINTER(LdpcTuning)]
+    lib.ldpc_graph_set_tuning.restype = ctypes.c_int
+    lib.ldpc_graph_get_tuning.argtypes = [_vp, ctypes.POINTER(LdpcTuning)]
+    lib.ldpc_graph_get_tuning.restype = ctypes.c_int
+    lib.ldpc_autotune_workspace_bytes.argtypes = [_vp, _i32]
+    lib.ldpc_autotune_workspace_bytes.restype = ctypes.c_size_t
+    lib.ldpc_autotune.argtypes = [_vp, _i32, _i32, ctypes.c_float, _vp, ctypes.c_size_t, _vp,
+                                  ctypes.POINTER(LdpcTuning)]
+    lib.ldpc_autotune.restype = ctypes.c_int
     lib.ldpc_timing_enable.argtypes = [ctypes.c_int]
     lib.ldpc_timing_enable.restype = ctypes.c_int
     lib.ldpc_timing_read.argtypes = [_i32, ctypes.POINTER(ctypes.c_double), _i64p]
@@ -332,3 +350,89 @@ def minsum_decode_multi(jobs, max_iter: int, flags: int = 0, want_post: bool = T
     if st:
         raise LdpcError(st, "ldpc_minsum_decode_multi")
     return [o for _, o in results]
+
+
+class CapturedDecode:
+    """A decode call captured once into a HIP graph (torch.cuda.CUDAGraph)
+    and replayed.  Inputs and outputs are static buffers: copy new LLRs into
+    ``.llr`` (or the per-job LLR tensors of a multi-code capture) and call
+    ``replay()``.
+
+    jobs: a Graph (single code) or a list of Graphs (one multi-code launch);
+    batches: B, or one B per graph."""
+
+    def __init__(self, jobs, batches, max_iter: int, flags: int = 0, want_post: bool = True,
+                 alpha: torch.Tensor | None = None, beta: torch.Tensor | None = None):
+        self.multi = isinstance(jobs, (list, tuple))
+        graphs = list(jobs) if self.multi else [jobs]
+        Bs = list(batches) if self.multi else [batches]
+        dev = graphs[0].device
+        self.graphs, self.max_iter, self.flags = graphs, max_iter, flags
+        self.alpha, self.beta = alpha, beta
+        self.llrs = [torch.zeros((B, g.n), dtype=torch.float32, device=dev) for g, B in zip(graphs, Bs)]
+        self.outs = [_outputs(B, g.n, dev, want_post) for g, B in zip(graphs, Bs)]
+        if self.multi:
+            need = int(load_library().ldpc_multi_workspace_bytes(len(graphs)))
+        else:
+            need = workspace_bytes(graphs[0], Bs[0], flags)
+        self.ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+        side = torch.cuda.Stream(device=dev)  # default priority
+        side.wait_stream(torch.cuda.current_stream(dev))
+        with torch.cuda.stream(side):
+            self._run()  # warm-up outside the capture (kernel attributes, lazy loading)
+        torch.cuda.current_stream(dev).wait_stream(side)
+        torch.cuda.synchronize(dev)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self._run()
+
+    @property
+    def llr(self):
+        return self.llrs[0]
+
+    def _run(self):
+        if self.multi:
+            minsum_decode_multi(list(zip(self.graphs, self.llrs)), self.max_iter, self.flags, workspace=self.ws,
+                                outs=self.outs)
+        elif self.alpha is not None:
+            nms_decode(self.graphs[0], self.llrs[0], self.max_iter, self.alpha, self.beta, flags=self.flags,
+                       workspace=self.ws, out=self.outs[0])
+        else:
+            minsum_decode(self.graphs[0], self.llrs[0], self.max_iter, flags=self.flags, workspace=self.ws,
+                          out=self.outs[0])
+
+    def replay(self):
+        self.graph.replay()
+        return self.outs if self.multi else self.outs[0]
+
+
+def set_tuning(g: Graph, path: int | None = None, variant: int = -1, wg_per_cu: int = 0, stream_waves: int = 4):
+    """ldpc_graph_set_tuning; path None clears the record."""
+    lib = load_library()
+    t = None if path is None else ctypes.byref(LdpcTuning(path, variant, wg_per_cu, stream_waves, 0.0))
+    st = lib.ldpc_graph_set_tuning(g.handle, t)
+    if st:
+        raise LdpcError(st, "ldpc_graph_set_tuning")
+
+
+def get_tuning(g: Graph) -> dict:
+    t = LdpcTuning()
+    st = load_library().ldpc_graph_get_tuning(g.handle, ctypes.byref(t))
+    if st:
+        raise LdpcError(st, "ldpc_graph_get_tuning")
+    return t.as_dict()
+
+
+def autotune(g: Graph, B: int, max_iter: int, ebn0_db: float) -> dict:
+    """ldpc_autotune: time the launch choices on B synthetic frames and keep
+    the fastest in the graph's tuning record.  Returns it as a dict."""
+    lib = load_library()
+    need = int(lib.ldpc_autotune_workspace_bytes(g.handle, int(B)))
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device=g.device)
+    best = LdpcTuning()
+    with torch.cuda.device(g.device):
+        st = lib.ldpc_autotune(g.handle, int(B), int(max_iter), float(ebn0_db), _ptr(ws), ws.numel(),
+                               _stream(g.device), ctypes.byref(best))
+    if st:
+        raise LdpcError(st, "ldpc_autotune")
+    return best.as_dict()

@@ -1,0 +1,62 @@
+"""Launch choices (GPU): every on-chip variant, occupancy cap and streaming
+workgroup size gives the same outputs; the autotuner keeps a valid choice."""
+import itertools
+
+import numpy as np
+import pytest
+
+from paper_2507_10424_amd import workloads as wl
+from parity import assert_parity, oracle_decode
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tdev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch, torch.device("cuda:0")
+
+
+def test_all_launch_choices_agree(tdev):
+    torch, dev = tdev
+    from paper_2507_10424_amd import ldpc
+    H = wl.regular_ldpc(1024, 512, 3, 6, seed=2)
+    g = ldpc.build_graph(torch.from_numpy(H).to(dev))
+    llr_np = wl.bpsk_awgn_llr(None, 1.75, 0.5, seed=31, n=1024, batch=900)
+    llr = torch.from_numpy(llr_np).to(dev)
+    ref = oracle_decode(H, llr_np, 40)
+    tried = 0
+    for v, wpc in itertools.product(range(8), (0, 1, 3)):
+        try:
+            ldpc.set_tuning(g, 1, variant=v, wg_per_cu=wpc)
+        except ldpc.LdpcError as e:
+            assert e.status == -6
+            continue
+        out = ldpc.minsum_decode(g, llr, 40)
+        torch.cuda.synchronize()
+        assert_parity(tuple(t.cpu().numpy() for t in out), ref, f"variant {v} wpc {wpc}")
+        tried += 1
+    for waves in (1, 2, 4, 8):
+        ldpc.set_tuning(g, 2, stream_waves=waves)
+        out = ldpc.minsum_decode(g, llr, 40)
+        torch.cuda.synchronize()
+        assert_parity(tuple(t.cpu().numpy() for t in out), ref, f"stream waves {waves}")
+    assert tried >= 4 * 3
+    ldpc.set_tuning(g, None)
+    assert ldpc.get_tuning(g)["path"] == 0
+
+
+def test_autotune_keeps_valid_choice(tdev):
+    torch, dev = tdev
+    from paper_2507_10424_amd import ldpc
+    H = wl.regular_ldpc(96, 48, 3, 6, seed=1)
+    g = ldpc.build_graph(torch.from_numpy(H).to(dev))
+    best = ldpc.autotune(g, 4000, 20, 2.0)
+    assert best["path"] in (1, 2) and best["ms"] > 0
+    assert ldpc.get_tuning(g)["path"] == best["path"]
+    llr_np = wl.bpsk_awgn_llr(None, 2.0, 0.5, seed=100, n=96, batch=1000)
+    out = ldpc.minsum_decode(g, torch.from_numpy(llr_np).to(dev), 20)
+    torch.cuda.synchronize()
+    assert_parity(tuple(t.cpu().numpy() for t in out), oracle_decode(H, llr_np, 20), "autotuned")
