@@ -37,7 +37,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="regular1024", choices=["regular1024", "qc64800", "regular96"])
+    ap.add_argument("--config", default="regular1024", choices=["regular1024", "qc64800", "regular96", "multi8"])
+    ap.add_argument("--no-autotune", action="store_true", help="skip the autotuner (library defaults)")
     ap.add_argument("--path", default="auto", choices=["auto", "stream", "onchip"])
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -57,6 +58,11 @@ def workload(name):
         return dict(name="irregular QC n=64800 m=32400 Z=360, 4096 all-zero frames x Eb/N0 1.0..1.6 dB, L=50, "
                          "early exit", H=H, batch=4096, ebn0=[1.0, 1.2, 1.4, 1.6], L=50, rate=0.5,
                     random_cw=False, seed_cw=0, seed_noise=500)
+    if name == "multi8":
+        fam = wl.qc_multi_code_family(seed=7)
+        return dict(name="8 irregular QC codes n in {576,1152,1728,2304}, rates 1/2..5/6, Z in {24,48,72,96}, "
+                         "batches 512..16384 (49152 frames), all-zero codewords at 2 dB, L=50, one launch",
+                    family=fam, ebn0=[2.0], L=50, seed_noise=700)
     H = wl.regular_ldpc(96, 48, 3, 6, seed=1)
     return dict(name="(3,6)-regular n=96 m=48, 1000 all-zero frames at 2 dB, L=20", H=H, batch=1000, ebn0=[2.0],
                 L=20, rate=0.5, random_cw=False, seed_cw=0, seed_noise=100)
@@ -81,6 +87,8 @@ def main():
                                      ctypes.POINTER(ctypes.c_int64)]
 
     W = workload(args.config)
+    if args.config == "multi8":
+        return bench_multi(args, W, dev, lib)
     H = W["H"]
     m, n = H.shape
     B, L = W["batch"], W["L"]
@@ -101,6 +109,11 @@ def main():
     torch.cuda.synchronize()
     log(f"[bench] inputs ready on the GPU in {time.time() - t0:.1f} s ({len(llrs)} x {B} x {n})")
 
+    tuning = None
+    if not args.no_autotune and args.path == "auto":
+        ta = time.time()
+        tuning = ldpc.autotune(g, min(B, 16384), L, 2.0 if args.config != "qc64800" else 1.2)
+        log(f"[bench] autotuned in {time.time() - ta:.1f} s: {tuning}")
     ws = torch.empty(max(1, ldpc.workspace_bytes(g, B, flags)), dtype=torch.uint8, device=dev)
     outs = [ldpc._outputs(B, n, dev, True) for _ in llrs]
 
@@ -217,10 +230,77 @@ def main():
         "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": W["name"], "n": n, "m": m, "edges": E, "batch": B, "batches_per_step": len(llrs),
-                   "ebn0_db": W["ebn0"], "max_iter": L, "path": args.path},
+                   "ebn0_db": W["ebn0"], "max_iter": L, "path": args.path, "tuning": tuning},
         "edge_msg_per_s": edge_msgs, "info_gbit_s": round(gbits * k_info / n, 3) if k_info else None,
         "mean_iters": round(tot_iters / frames_step, 3), "per_point": per_point,
         "roofline": roofline, "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_multi(args, W, dev, lib):
+    """Eight codes, one persistent launch per step (ldpc_minsum_decode_multi);
+    also times one launch per code for comparison."""
+    import ctypes
+    import torch
+    from paper_2507_10424_amd import ldpc
+    from paper_2507_10424_amd import workloads as wl
+    fam, L = W["family"], W["L"]
+    graphs, llrs = [], []
+    for k, c in enumerate(fam):
+        graphs.append(ldpc.build_graph(torch.from_numpy(c["H"]).to(dev)))
+        llrs.append(wl.bpsk_awgn_llr_torch(None, W["ebn0"][0], c["rate"], W["seed_noise"] + k, dev, n=c["n"],
+                                           batch=c["batch"]))
+    jobs = list(zip(graphs, llrs))
+    outs = [ldpc._outputs(c["batch"], c["n"], dev, True) for c in fam]
+    ws = torch.empty(int(lib.ldpc_multi_workspace_bytes(len(jobs))), dtype=torch.uint8, device=dev)
+    frames = sum(c["batch"] for c in fam)
+    bits = sum(c["batch"] * c["n"] for c in fam)
+
+    def step_multi():
+        ldpc.minsum_decode_multi(jobs, L, workspace=ws, outs=outs)
+
+    def step_each():
+        for (g, x), o in zip(jobs, outs):
+            ldpc.minsum_decode(g, x, L, workspace=ws, out=o)
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record()
+        for _ in range(args.steps):
+            fn()
+        ev1.record()
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / args.steps
+
+    ms_each = timed(step_each)
+    ms_multi = timed(step_multi)
+    gbits = bits / (ms_multi * 1e-3) / 1e9
+    log(f"[bench] multi-code: one launch {ms_multi:.3f} ms/step ({gbits:.2f} Gbit/s), "
+        f"one launch per code {ms_each:.3f} ms/step")
+    iters = sum(int(o[2].to(torch.int64).sum()) for o in outs)
+    edges_iters = sum(int(o[2].to(torch.int64).sum()) * g.E for o, g in zip(outs, graphs))
+    per_code = []
+    for c, o in zip(fam, outs):
+        fe = int((o[0] != 0).any(dim=1).sum())
+        per_code.append(dict(n=c["n"], rate=round(c["rate"], 4), Z=c["Z"], batch=c["batch"], fer=fe / c["batch"],
+                             mean_iters=round(float(o[2].float().mean()), 3)))
+    ops = 12.0 * edges_iters
+    achieved = ops / (ms_multi * 1e-3) / 1e12
+    line = {
+        "metric": "coded Gbit/s & edge-msg/s (% HBM BW); neural vs plain Min-Sum at equal FER",
+        "value": round(gbits, 3), "unit": "Gbit/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_multi, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": W["name"], "frames": frames, "max_iter": L, "ebn0_db": W["ebn0"]},
+        "edge_msg_per_s": 2.0 * edges_iters / (ms_multi * 1e-3), "mean_iters": round(iters / frames, 3),
+        "ms_per_step_one_launch_per_code": round(ms_each, 4), "per_code": per_code,
+        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
+                     "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None, "kernel": "onchip_multi"},
+        "cpu_baseline": None,
     }
     print(json.dumps(line), flush=True)
 

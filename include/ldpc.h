@@ -207,9 +207,11 @@ int ldpc_nms_decode(const ldpc_graph *g, const float *llr_dev, int32_t B, int32_
  * constant and the clip max(v, 0) passes the gradient where v > 0.  Sums over
  * frames are taken in a fixed order (deterministic).
  *
+ * The per-frame state lives in LDS when it fits one workgroup; otherwise it
+ * lives in the workspace (4 n + 2 E + ckpt_every (n + E) floats per frame).
  * Errors: LDPC_EINVAL (null pointers, B, T or ckpt_every < 1),
- * LDPC_EWORKSPACE, LDPC_EUNSUPPORTED (more than 8 degree classes, or the
- * per-frame state does not fit the LDS of one workgroup), LDPC_EHIP.
+ * LDPC_EWORKSPACE, LDPC_EUNSUPPORTED (more than 8 degree classes),
+ * LDPC_EHIP.
  */
 size_t ldpc_nms_train_workspace_bytes(const ldpc_graph *g, int32_t B, int32_t T, int32_t ckpt_every);
 int ldpc_nms_train_forward(const ldpc_graph *g, const float *llr_dev, const uint8_t *target_dev, int32_t B,
@@ -251,6 +253,8 @@ int ldpc_adam_step(float *param_dev, const float *grad_dev, float *m1_dev, float
  *                 thread), -1 for the first that fits
  *   wg_per_cu     on-chip workgroups per CU, 0 for the occupancy limit
  *   stream_waves  wavefronts per workgroup of the streaming kernels (1..8)
+ *   waves_per_simd  on-chip register budget: 0 the compiler's, 4 at least four
+ *                 resident waves per SIMD (fewer registers per thread)
  *   ms            ldpc_autotune: mean time of one decode of the tuning batch
  * LDPC_FORCE_STREAM / LDPC_FORCE_ONCHIP still override the path.
  */
@@ -259,6 +263,7 @@ typedef struct ldpc_tuning {
     int32_t variant;
     int32_t wg_per_cu;
     int32_t stream_waves;
+    int32_t waves_per_simd;
     float ms;
 } ldpc_tuning;
 
@@ -272,8 +277,9 @@ int ldpc_graph_get_tuning(const ldpc_graph *g, ldpc_tuning *t);
  * Autotuner: generates B all-zero frames at ebn0_db on the device, times one
  * warm-up and three decodes (at most max_iter iterations, early exit) for
  * every launch choice that applies to the graph (each fitting on-chip
- * variant with 0..4 workgroups per CU, the streaming path with 1, 2, 4, 8
- * wavefronts per workgroup), and stores the fastest in the graph's tuning
+ * variant, both register budgets, 0..4 workgroups per CU; the streaming path
+ * with 1, 2, 4, 8 wavefronts per workgroup), and stores the fastest in the
+ * graph's tuning
  * record (also returned in *best if non-null).  It synchronises `stream`
  * and creates two HIP events; do not capture it.  The workspace needs
  * ldpc_autotune_workspace_bytes(g, B) bytes.

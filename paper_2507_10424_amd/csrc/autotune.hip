@@ -2,9 +2,10 @@
 // synthetic frames and keeps the fastest in the graph's tuning record.
 //
 // Choices: the on-chip path with each kernel variant that fits the graph
-// (exact or masked degree templates, one or two rows per thread) and a cap
-// on workgroups per CU (occupancy limit, 1, 2, 3, 4); the streaming path
-// with 1, 2, 4 or 8 wavefronts per workgroup of its check and bit kernels.
+// (exact or masked degree templates, one or two rows per thread), a register
+// budget (the compiler's, or at least 4 waves per SIMD) and a cap on
+// workgroups per CU (occupancy limit, 1, 2, 3, 4); the streaming path with
+// 1, 2, 4 or 8 wavefronts per workgroup of its check and bit kernels.
 #include <vector>
 
 #include "ldpc_internal.h"
@@ -68,10 +69,12 @@ extern "C" int ldpc_graph_set_tuning(ldpc_graph *g, const ldpc_tuning *t) {
     if (t->path == 1 && t->variant >= 0 && !onchip_variant_fits(*g, t->variant)) return LDPC_EUNSUPPORTED;
     if (t->path == 1 && t->variant < 0 && !onchip_fits(*g)) return LDPC_EUNSUPPORTED;
     if (t->path == 2 && (t->stream_waves < 1 || t->stream_waves > 8)) return LDPC_EINVAL;
+    if (t->path == 1 && t->waves_per_simd != 0 && t->waves_per_simd != 4) return LDPC_EINVAL;
     g->tuning.set = true;
     g->tuning.path = t->path;
     g->tuning.variant = t->variant;
     g->tuning.wg_per_cu = t->wg_per_cu;
+    g->tuning.waves_per_simd = t->path == 1 ? t->waves_per_simd : 0;
     g->tuning.stream_waves = t->path == 2 ? t->stream_waves : 4;
     return LDPC_OK;
 }
@@ -82,6 +85,7 @@ extern "C" int ldpc_graph_get_tuning(const ldpc_graph *g, ldpc_tuning *t) {
     t->variant = g->tuning.variant;
     t->wg_per_cu = g->tuning.wg_per_cu;
     t->stream_waves = g->tuning.stream_waves;
+    t->waves_per_simd = g->tuning.waves_per_simd;
     t->ms = 0.0f;
     return LDPC_OK;
 }
@@ -110,9 +114,10 @@ extern "C" int ldpc_autotune(ldpc_graph *g, int32_t B, int32_t max_iter, float e
     std::vector<ldpc_tuning> cands;
     for (int v = 0; v < onchip_num_variants(); ++v) {
         if (!onchip_variant_fits(*g, v)) continue;
-        for (int wpc : {0, 1, 2, 3, 4}) cands.push_back(ldpc_tuning{1, v, wpc, 4, 0.0f});
+        for (int wps : {0, 4})
+            for (int wpc : {0, 1, 2, 3, 4}) cands.push_back(ldpc_tuning{1, v, wpc, 4, wps, 0.0f});
     }
-    for (int waves : {1, 2, 4, 8}) cands.push_back(ldpc_tuning{2, -1, 0, waves, 0.0f});
+    for (int waves : {1, 2, 4, 8}) cands.push_back(ldpc_tuning{2, -1, 0, waves, 0, 0.0f});
 
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return LDPC_EHIP;

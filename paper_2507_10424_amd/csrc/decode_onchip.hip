@@ -353,8 +353,12 @@ __device__ __forceinline__ void run_variant(const Job &J, int32_t L, int32_t ear
 }
 static_assert(kNumVariants == 8, "run_variant dispatches eight variants");
 
-// One graph per launch, one variant instantiated.
-template <int V> __global__ __launch_bounds__(kMaxThreads) void k_onchip(const Job J, int32_t L, int32_t early) {
+// One graph per launch, one variant instantiated.  W > 0 asks the compiler
+// for at least W waves per SIMD (fewer registers per thread, more resident
+// waves to hide LDS latency); W = 0 leaves the register budget to it.
+template <int V, int W>
+__global__ __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(W > 0 ? W : 1))) void k_onchip(
+    const Job J, int32_t L, int32_t early) {
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
     run_v<V>(J, L, early, lds);
 }
@@ -376,8 +380,11 @@ __global__ __launch_bounds__(kMaxThreads) void k_onchip_multi(const JobTable jt,
 }
 
 using KernelFn = void (*)(const Job, int32_t, int32_t);
-const KernelFn kKernels[] = {&k_onchip<0>, &k_onchip<1>, &k_onchip<2>, &k_onchip<3>,
-                             &k_onchip<4>, &k_onchip<5>, &k_onchip<6>, &k_onchip<7>};
+const KernelFn kKernels[2][8] = {
+    {&k_onchip<0, 0>, &k_onchip<1, 0>, &k_onchip<2, 0>, &k_onchip<3, 0>, &k_onchip<4, 0>, &k_onchip<5, 0>,
+     &k_onchip<6, 0>, &k_onchip<7, 0>},
+    {&k_onchip<0, 4>, &k_onchip<1, 4>, &k_onchip<2, 4>, &k_onchip<3, 4>, &k_onchip<4, 4>, &k_onchip<5, 4>,
+     &k_onchip<6, 4>, &k_onchip<7, 4>}};
 
 // Threads: whole wavefronts, enough for RPT rows and CPT bits per thread.
 int threads_for(const ldpc_graph &g, const Variant &v) {
@@ -473,7 +480,7 @@ int onchip_decode(const ldpc_graph &g, const float *llr, int32_t B, int32_t L, u
     if (!onchip_fits(g)) return LDPC_EUNSUPPORTED;
     if (ws == nullptr || ws_bytes < onchip_workspace_bytes(g, B)) return LDPC_EWORKSPACE;
     const int v = pick(g);
-    const KernelFn fn = kKernels[v];
+    const KernelFn fn = kKernels[(g.tuning.set && g.tuning.waves_per_simd == 4) ? 1 : 0][v];
     const int threads = threads_for(g, kVariants[v]);
     const size_t lds = onchip_lds_bytes(g);
     int grid = 0;

@@ -36,6 +36,7 @@ struct ldpc_graph {
         int path = 0;         // 1 on-chip, 2 streaming
         int variant = -1;     // on-chip kernel variant
         int wg_per_cu = 0;    // on-chip workgroups per CU (0: occupancy limit)
+        int waves_per_simd = 0; // on-chip register budget: 0 compiler's, 4 at least 4 waves per SIMD
         int stream_waves = 4; // wavefronts per workgroup of the streaming kernels
     } tuning;
 };

@@ -8,7 +8,8 @@
 // (binary cross-entropy of every iteration's posterior against the
 // transmitted bits; P(bit = 1) = sigmoid(-s)).
 //
-// Forward: one workgroup per frame, state in LDS, the same binary32
+// Forward: one workgroup per frame, state in LDS (or, for codes whose state
+// does not fit, in a per-frame region of the workspace), the same binary32
 // arithmetic as the decoder (so the posteriors equal those of
 // ldpc_nms_decode with LDPC_NO_EARLY_EXIT bit for bit).  Every K iterations
 // the state (s, eta) is written to a checkpoint in the workspace.
@@ -113,16 +114,20 @@ __device__ void bit_pass(const int32_t *__restrict__ col_ptr, const int32_t *__r
     }
 }
 
+// ONCHIP: the per-frame state lives in LDS; otherwise in a per-frame region
+// of `scratch` (global memory), for codes whose state does not fit.
+template <bool ONCHIP>
 __global__ __launch_bounds__(kThreads) void k_nms_fwd(
     const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx, const int32_t *__restrict__ col_ptr,
     const int32_t *__restrict__ csc_edge, const int32_t *__restrict__ row_class, int32_t m, int32_t n, int32_t E,
     int32_t ncls, const float *__restrict__ llr, const uint8_t *__restrict__ target, int32_t T, int32_t K,
     const float *__restrict__ alpha, const float *__restrict__ beta, float *__restrict__ ckpt,
-    float *__restrict__ loss_part, float *__restrict__ post) {
+    float *__restrict__ loss_part, float *__restrict__ post, float *__restrict__ scratch) {
     extern __shared__ float sm[];
     __shared__ float red[16];
-    float *s = sm, *r = s + n, *eta = r + n, *x = eta + E;
     const int32_t f = blockIdx.x;
+    float *base = ONCHIP ? sm : scratch + (size_t)f * (2ull * n + 2ull * E);
+    float *s = base, *r = s + n, *eta = r + n, *x = eta + E;
     const int32_t nck = (T + K - 1) / K;
     for (int32_t j = threadIdx.x; j < n; j += blockDim.x) {
         const float v = llr[(size_t)f * n + j];
@@ -154,18 +159,20 @@ __global__ __launch_bounds__(kThreads) void k_nms_fwd(
     if (threadIdx.x == 0) loss_part[f] = tot;
 }
 
+template <bool ONCHIP>
 __global__ __launch_bounds__(kThreads) void k_nms_bwd(
     const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx, const int32_t *__restrict__ col_ptr,
     const int32_t *__restrict__ csc_edge, const int32_t *__restrict__ row_class, int32_t m, int32_t n, int32_t E,
     int32_t ncls, const float *__restrict__ llr, const uint8_t *__restrict__ target, int32_t T, int32_t K,
     const float *__restrict__ alpha, const float *__restrict__ beta, const float *__restrict__ ckpt, float scale,
-    float *__restrict__ gpart /* [B][2][T][ncls] */, float *__restrict__ gllr) {
+    float *__restrict__ gpart /* [B][2][T][ncls] */, float *__restrict__ gllr, float *__restrict__ scratch) {
     extern __shared__ float sm[];
     __shared__ float red[16];
-    // LDS: s, r, gs, gr (n each); eta, gxn (E each); xbuf (K*E), sbuf (K*n)
-    float *s = sm, *r = s + n, *gs = r + n, *gr = gs + n, *eta = gr + n, *gxn = eta + E, *xbuf = gxn + E,
-          *sbuf = xbuf + (size_t)K * E;
     const int32_t f = blockIdx.x;
+    // state: s, r, gs, gr (n each); eta, gxn (E each); xbuf (K*E), sbuf (K*n)
+    float *base = ONCHIP ? sm : scratch + (size_t)f * (4ull * n + 2ull * E + (size_t)K * E + (size_t)K * n);
+    float *s = base, *r = s + n, *gs = r + n, *gr = gs + n, *eta = gr + n, *gxn = eta + E, *xbuf = gxn + E,
+          *sbuf = xbuf + (size_t)K * E;
     const int32_t nck = (T + K - 1) / K;
     float *gp = gpart + (size_t)f * 2 * T * ncls;
     for (int32_t j = threadIdx.x; j < n; j += blockDim.x) {
@@ -336,8 +343,15 @@ __global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float
 }
 
 struct TrainWs {
-    float *ckpt, *loss_part, *gpart;
+    float *ckpt, *loss_part, *gpart, *scratch;
 };
+
+size_t fwd_lds(const ldpc_graph &g) { return 4ull * (2ull * g.n + 2ull * g.E); }
+size_t bwd_lds(const ldpc_graph &g, int32_t K) {
+    return 4ull * (4ull * g.n + 2ull * g.E + (size_t)K * g.E + (size_t)K * g.n);
+}
+// the backward needs the larger state; both kernels use LDS or both global
+bool train_onchip(const ldpc_graph &g, int32_t K) { return bwd_lds(g, K) + 1024 <= (size_t)g.lds_max; }
 
 TrainWs carve_train(const ldpc_graph &g, int32_t B, int32_t T, int32_t K, void *base, size_t *total) {
     const int32_t nck = (T + K - 1) / K;
@@ -351,6 +365,7 @@ TrainWs carve_train(const ldpc_graph &g, int32_t B, int32_t T, int32_t K, void *
     const size_t o_ck = take((size_t)B * nck * ((size_t)g.n + (size_t)g.E) * 4);
     const size_t o_lp = take((size_t)B * 4);
     const size_t o_gp = take((size_t)B * 2 * T * ncls * 4);
+    const size_t o_sc = take(train_onchip(g, K) ? 0 : (size_t)B * bwd_lds(g, K));
     if (total) *total = off;
     TrainWs w{};
     if (base) {
@@ -358,20 +373,15 @@ TrainWs carve_train(const ldpc_graph &g, int32_t B, int32_t T, int32_t K, void *
         w.ckpt = (float *)(b + o_ck);
         w.loss_part = (float *)(b + o_lp);
         w.gpart = (float *)(b + o_gp);
+        w.scratch = (float *)(b + o_sc);
     }
     return w;
-}
-
-size_t fwd_lds(const ldpc_graph &g) { return 4ull * (2ull * g.n + 2ull * g.E); }
-size_t bwd_lds(const ldpc_graph &g, int32_t K) {
-    return 4ull * (4ull * g.n + 2ull * g.E + (size_t)K * g.E + (size_t)K * g.n);
 }
 
 int train_check(const ldpc_graph *g, const float *llr, int32_t B, int32_t T, int32_t K, const float *alpha,
                 const float *beta) {
     if (!g || !llr || !alpha || !beta || B < 1 || T < 1 || K < 1) return LDPC_EINVAL;
     if ((int)g->class_degrees.size() > kMaxClasses) return LDPC_EUNSUPPORTED;
-    if (bwd_lds(*g, K) + 1024 > (size_t)g->lds_max) return LDPC_EUNSUPPORTED;
     return LDPC_OK;
 }
 
@@ -397,14 +407,15 @@ extern "C" int ldpc_nms_train_forward(const ldpc_graph *g, const float *llr_dev,
     size_t need = 0;
     TrainWs w = carve_train(*g, B, T, ckpt_every, ws_dev, &need);
     if (!ws_dev || ws_bytes < need) return LDPC_EWORKSPACE;
-    const size_t lds = fwd_lds(*g);
-    if (hipFuncSetAttribute((const void *)k_nms_fwd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
-        hipSuccess)
+    const bool on = train_onchip(*g, ckpt_every);
+    const size_t lds = on ? fwd_lds(*g) : 0;
+    auto fn = on ? &k_nms_fwd<true> : &k_nms_fwd<false>;
+    if (on && hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
+                  hipSuccess)
         return LDPC_EHIP;
-    k_nms_fwd<<<B, kThreads, lds, stream>>>(g->row_ptr, g->col_idx, g->col_ptr, g->csc_edge, g->row_class, g->m,
-                                            g->n, (int32_t)g->E, (int32_t)g->class_degrees.size(), llr_dev,
-                                            target_dev, T, ckpt_every, alpha_dev, beta_dev, w.ckpt, w.loss_part,
-                                            post_dev);
+    fn<<<B, kThreads, lds, stream>>>(g->row_ptr, g->col_idx, g->col_ptr, g->csc_edge, g->row_class, g->m, g->n,
+                                     (int32_t)g->E, (int32_t)g->class_degrees.size(), llr_dev, target_dev, T,
+                                     ckpt_every, alpha_dev, beta_dev, w.ckpt, w.loss_part, post_dev, w.scratch);
     k_sum_frames<<<1, 64, 0, stream>>>(w.loss_part, B, 1, 0, 1, 1.0f / ((float)B * (float)g->n), loss_dev);
     return hipGetLastError() == hipSuccess ? LDPC_OK : LDPC_EHIP;
 }
@@ -419,15 +430,17 @@ extern "C" int ldpc_nms_train_backward(const ldpc_graph *g, const float *llr_dev
     size_t need = 0;
     TrainWs w = carve_train(*g, B, T, ckpt_every, ws_dev, &need);
     if (!ws_dev || ws_bytes < need) return LDPC_EWORKSPACE;
-    const size_t lds = bwd_lds(*g, ckpt_every);
-    if (hipFuncSetAttribute((const void *)k_nms_bwd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
-        hipSuccess)
+    const bool on = train_onchip(*g, ckpt_every);
+    const size_t lds = on ? bwd_lds(*g, ckpt_every) : 0;
+    auto fn = on ? &k_nms_bwd<true> : &k_nms_bwd<false>;
+    if (on && hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
+                  hipSuccess)
         return LDPC_EHIP;
     const int32_t ncls = (int32_t)g->class_degrees.size();
     const float scale = grad_loss / ((float)B * (float)g->n);
-    k_nms_bwd<<<B, kThreads, lds, stream>>>(g->row_ptr, g->col_idx, g->col_ptr, g->csc_edge, g->row_class, g->m,
-                                            g->n, (int32_t)g->E, ncls, llr_dev, target_dev, T, ckpt_every, alpha_dev,
-                                            beta_dev, w.ckpt, scale, w.gpart, gllr_dev);
+    fn<<<B, kThreads, lds, stream>>>(g->row_ptr, g->col_idx, g->col_ptr, g->csc_edge, g->row_class, g->m, g->n,
+                                     (int32_t)g->E, ncls, llr_dev, target_dev, T, ckpt_every, alpha_dev, beta_dev,
+                                     w.ckpt, scale, w.gpart, gllr_dev, w.scratch);
     const int32_t width = T * ncls;
     k_sum_frames<<<(width + 63) / 64, 64, 0, stream>>>(w.gpart, B, 2 * width, 0, width, 1.0f, galpha_dev);
     k_sum_frames<<<(width + 63) / 64, 64, 0, stream>>>(w.gpart, B, 2 * width, width, width, 1.0f, gbeta_dev);

@@ -185,3 +185,31 @@ def test_training_gains_over_plain(tdev):
     note(f"[nms-train] 2 dB, 10 iterations: plain FER {fe_p / 8192:.4f} BER {be_p / 8192 / 1024:.2e}; "
          f"learned FER {fe_n / 8192:.4f} BER {be_n / 8192 / 1024:.2e}")
     assert be_n < be_p and fe_n <= fe_p
+
+
+def test_gradient_with_state_in_device_memory(tdev):
+    """A code whose per-frame training state exceeds one workgroup's LDS
+    (QC, 180 x 90 base graph of the n = 64800 profile lifted by Z = 36)."""
+    torch, dev = tdev
+    from paper_2507_10424_amd import ldpc
+    cd = np.concatenate([np.full(36, 8), np.full(54, 3), np.full(90, 2)])
+    cd = cd[np.random.default_rng(5).permutation(cd.size)]
+    H = wl.qc_irregular_ldpc(180, 90, 36, cd, seed=9)
+    C = oracle.check_degrees(H).size
+    T, K, B = 4, 2, 3
+    a, b = _weights(T, C, 12)
+    llr = wl.bpsk_awgn_llr(None, 1.4, 0.5, seed=13, n=H.shape[1], batch=B)
+    g = _graph(torch, dev, H)
+    at, bt, lt = (torch.from_numpy(x).to(dev) for x in (a, b, llr))
+    ws = torch.empty(ldpc.train_workspace_bytes(g, B, T, K), dtype=torch.uint8, device=dev)
+    loss, post = ldpc.nms_train_forward(g, lt, at, bt, K, ws, want_post=True)
+    ga, gb, _ = ldpc.nms_train_backward(g, lt, at, bt, K, ws)
+    torch.cuda.synchronize()
+    _, opost, _, _ = oracle.nms_decode(H, llr, T, a, b, early_exit=False)
+    assert np.array_equal(post.cpu().numpy(), opost)
+    ref, oa, ob, _ = oracle.nms_train_loss_grad(H, llr.astype(np.float64), a.astype(np.float64),
+                                                b.astype(np.float64))
+    assert abs(float(loss) - ref) <= 2e-5 * abs(ref)
+    for got, want in [(ga, oa), (gb, ob)]:
+        got = got.cpu().numpy().astype(np.float64)
+        assert np.all(np.abs(got - want) <= 2e-3 * np.abs(want) + 2e-4 * np.abs(want).max() + 1e-9)

@@ -28,22 +28,22 @@ def test_all_launch_choices_agree(tdev):
     llr = torch.from_numpy(llr_np).to(dev)
     ref = oracle_decode(H, llr_np, 40)
     tried = 0
-    for v, wpc in itertools.product(range(8), (0, 1, 3)):
+    for v, wpc, wps in itertools.product(range(8), (0, 1, 3), (0, 4)):
         try:
-            ldpc.set_tuning(g, 1, variant=v, wg_per_cu=wpc)
+            ldpc.set_tuning(g, 1, variant=v, wg_per_cu=wpc, waves_per_simd=wps)
         except ldpc.LdpcError as e:
             assert e.status == -6
             continue
         out = ldpc.minsum_decode(g, llr, 40)
         torch.cuda.synchronize()
-        assert_parity(tuple(t.cpu().numpy() for t in out), ref, f"variant {v} wpc {wpc}")
+        assert_parity(tuple(t.cpu().numpy() for t in out), ref, f"variant {v} wpc {wpc} wps {wps}")
         tried += 1
     for waves in (1, 2, 4, 8):
         ldpc.set_tuning(g, 2, stream_waves=waves)
         out = ldpc.minsum_decode(g, llr, 40)
         torch.cuda.synchronize()
         assert_parity(tuple(t.cpu().numpy() for t in out), ref, f"stream waves {waves}")
-    assert tried >= 4 * 3
+    assert tried >= 4 * 3 * 2
     ldpc.set_tuning(g, None)
     assert ldpc.get_tuning(g)["path"] == 0
 
