@@ -32,6 +32,40 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def min_pair_ops(d: int) -> int:
+    """Instructions for the two smallest of d magnitudes with three-input
+    min / median forms: the first group of three takes 2 (min3, med3), each
+    further group of three 5 (min3, med3 of the group; min, max, min3 to join),
+    each leftover value 2 (min, med3)."""
+    if d <= 1:
+        return 0
+    if d == 2:
+        return 2
+    groups, rest = divmod(d, 3)
+    return 2 + 5 * (groups - 1) + 2 * rest
+
+
+def alu_ops_per_frame_iter(H) -> int:
+    """Lane-operations one Min-Sum iteration of one frame needs on gfx950.
+
+    Per check row of degree d >= 2: d subtractions x = s - eta; the min pair
+    of |x| (|x| is a free source modifier); ceil((d - 1) / 2) three-input XORs
+    for the sign parity and as many for the syndrome of the previous decision;
+    per edge a compare with min0, a select of min0 / min1 and one XOR-insert of
+    the sign (3 d).  Per bit of degree dv: dv additions (dv - 1 messages and
+    r).  Everything else a kernel issues (addresses, loop control, refills,
+    reductions, LDS waits) is overhead against this count."""
+    H = np.asarray(H)
+    dr = H.sum(axis=1).astype(np.int64)
+    dc = H.sum(axis=0).astype(np.int64)
+    ops = 0
+    for d, cnt in zip(*np.unique(dr[dr >= 2], return_counts=True)):
+        d = int(d)
+        ops += int(cnt) * (d + min_pair_ops(d) + 2 * ((d - 1 + 1) // 2) + 3 * d)
+    ops += int(dc.sum())
+    return ops
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -171,18 +205,19 @@ def main():
     # HBM-bound: per frame-iteration the check kernel moves 8E + 4n bytes
     # (4E + 4n in iteration 1, which reads no messages) and the bit kernel
     # 4E + 8n.  The on-chip kernel keeps the state in LDS and moves only frame
-    # I/O through HBM (4n in, 5n + 5 out); it is bound by VALU issue: 12 lane
-    # operations per edge and iteration (x = s - eta, |x|, max, 2 min, two
-    # sign XORs; magnitude compare and select, sign XOR and insert; one add in
-    # the bit sum) against 256 CUs x 64 lanes x 2.4 GHz.
+    # I/O through HBM (4n in, 5n + 5 out); it is bound by VALU issue: the
+    # lane-operations of alu_ops_per_frame_iter against 256 CUs x 64 lanes x
+    # 2.4 GHz.
     its = torch.cat(iters_all).to(torch.float64)
     if dom == "onchip":
-        ops = float(12.0 * E * its.sum())
+        ops_fi = alu_ops_per_frame_iter(H)
+        ops = float(ops_fi * its.sum())
         achieved = ops / (dom_ms * 1e-3) / 1e12
         peak = VALU_PEAK_TOPS
         io = float(frames_step * (9 * n + 5))
         roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "Tops/s",
                     "frac": round(achieved / peak, 4), "traffic": None, "kernel": dom,
+                    "lane_ops_per_frame_iter": ops_fi,
                     "kernel_ms_per_launch": round(dom_ms / dom_launches, 4), "launches_per_step": dom_launches,
                     "hbm_io_gb_s": round(io / (dom_ms * 1e-3) / 1e9, 1)}
     else:

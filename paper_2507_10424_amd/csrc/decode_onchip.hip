@@ -18,23 +18,26 @@
 // 8-byte LDS access serves both frames.
 //
 // Round (iteration t of each slot):
-//   check pass  per own row and slot: x_e = s_j - eta_prev_e; min0/min1 with
-//               integer min/max on the bit patterns of |x| (non-negative
-//               floats order like their bit patterns); sign parity = XOR of
-//               the sign bits of x; then eta_e = (|x_e| == min0 ? min1 : min0)
-//               with sign bit(x_e) XOR parity (Observations 1 and 2; on a tie
+//   check pass  per own row and slot: x_e = s_j - eta_prev_e; min0/min1 of
+//               |x| by a tournament of three-input min / median instructions
+//               (|x| is a free source modifier); sign parity = XOR of the sign
+//               bits of x; then eta_e = (|x_e| == min0 ? min1 : min0) with
+//               sign bit(x_e) XOR parity (Observations 1 and 2; on a tie
 //               min1 == min0, so every edge at the minimum may take min1).
 //               The XOR of the sign bits of the s values read per row is the
 //               syndrome of the previous hard decision.
 //   barrier     the per-slot "some row unsatisfied" bits are OR-reduced.
 //   decisions   a slot whose previous decision is a codeword (or that has run
 //               L iterations) writes its outputs and is refilled.
-//   bit pass    per own bit: s_j = (+0 + eta over the column in ascending
-//               check order) + r_j; a refilled slot gets s_j = r_j instead.
+//   bit pass    per own bit: s_j = (eta over the column in ascending check
+//               order) + r_j; a refilled slot gets s_j = r_j instead.
 //   barrier
 // Signs are read from sign bits: LLRs are loaded as r + 0.0f, which turns -0
 // into +0; after that no s or x can be -0, so the sign bit agrees with the
-// comparison v < 0 that defines sign() (sign(0) = +1).
+// comparison v < 0 that defines sign() (sign(0) = +1).  For the same reason
+// the column sum may start from its first message instead of from +0: the
+// two partial sums can differ only in the sign of a zero, and adding an r
+// that is not -0 gives the same s either way.
 #include <algorithm>
 
 #include "ldpc_internal.h"
@@ -59,6 +62,62 @@ size_t onchip_lds_bytes(const ldpc_graph &g) {
 }
 
 __global__ void k_zero_u32(uint32_t *p) { *p = 0u; }
+
+// Three-input XOR in one VALU instruction (v_bitop3_b32 with truth table
+// 0x96 = a ^ b ^ c), which the compiler does not form from XOR chains.
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    uint32_t r;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
+// XOR of N words with ceil((N - 1) / 2) instructions: three-input XORs, and
+// one two-input XOR when N is even.
+template <int N> __device__ __forceinline__ uint32_t xor_all(const uint32_t *v) {
+    if constexpr (N == 1) {
+        return v[0];
+    } else if constexpr (N == 2) {
+        return v[0] ^ v[1];
+    } else {
+        uint32_t acc = xor3(v[0], v[1], v[2]);
+#pragma unroll
+        for (int k = 3; k + 1 < N; k += 2) acc = xor3(acc, v[k], v[k + 1]);
+        if constexpr (N % 2 == 0) acc ^= v[N - 1];
+        return acc;
+    }
+}
+
+// Smallest and second smallest of N non-negative floats (min0 <= min1, equal
+// on a tie): groups of three give (min3, med3); a group joins the running pair
+// as min0 = min(m, gm), min1 = min3(max(m, gm), s, gs); single leftover values
+// join as min0 = min(m, v), min1 = med3(m, v, s).  Inputs are never NaN or
+// signalling, so the float min/max instructions are exact selections.
+template <int N> __device__ __forceinline__ void min_pair(const float *a, float &m, float &s) {
+    static_assert(N >= 1, "empty row");
+    if constexpr (N == 1) {
+        m = a[0];
+        s = __builtin_inff();
+    } else if constexpr (N == 2) {
+        m = fminf(a[0], a[1]);
+        s = fmaxf(a[0], a[1]);
+    } else {
+        m = fminf(fminf(a[0], a[1]), a[2]);
+        s = __builtin_amdgcn_fmed3f(a[0], a[1], a[2]);
+        int k = 3;
+#pragma unroll
+        for (; k + 3 <= N; k += 3) {
+            const float gm = fminf(fminf(a[k], a[k + 1]), a[k + 2]);
+            const float gs = __builtin_amdgcn_fmed3f(a[k], a[k + 1], a[k + 2]);
+            s = fminf(fminf(fmaxf(m, gm), s), gs);
+            m = fminf(m, gm);
+        }
+#pragma unroll
+        for (; k < N; ++k) {
+            s = __builtin_amdgcn_fmed3f(m, a[k], s);
+            m = fminf(m, a[k]);
+        }
+    }
+}
 
 __device__ __forceinline__ vf2 lds_ld(const unsigned char *base, uint32_t off) {
     return *reinterpret_cast<const vf2 *>(base + off);
@@ -156,7 +215,7 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
     int32_t fr[kF], tt[kF], gen[kF];
 #pragma unroll
     for (int q = 0; q < kF; ++q) {
-        fr[q] = sh->first[q];
+        fr[q] = __builtin_amdgcn_readfirstlane(sh->first[q]); // uniform: kept in scalar registers
         tt[q] = 1;
         gen[q] = 0;
     }
@@ -179,6 +238,14 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
     __syncthreads();
 
     for (int32_t round = 0;; ++round) {
+        // The slot state is the same in every lane; saying so keeps it in
+        // scalar registers and makes the branches on it scalar.
+#pragma unroll
+        for (int q = 0; q < kF; ++q) {
+            fr[q] = __builtin_amdgcn_readfirstlane(fr[q]);
+            tt[q] = __builtin_amdgcn_readfirstlane(tt[q]);
+            gen[q] = __builtin_amdgcn_readfirstlane(gen[q]);
+        }
         bool live = false;
 #pragma unroll
         for (int q = 0; q < kF; ++q) live |= fr[q] < B;
@@ -189,7 +256,7 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
             const int32_t d = RX ? DC : deg[r];
-            const bool rowv = deg[r] > 0;
+            const bool rowv = RX ? (tid + r * nt < m) : deg[r] > 0; // RX: recomputed, saves a register
             vf2 sv[DC];
 #pragma unroll
             for (int k = 0; k < DC; ++k) sv[k] = lds_ld(lds, sa[r][k]);
@@ -198,39 +265,43 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
                 // RX: every edge of a real row is valid; rows past m compute
                 // garbage that only reaches the padding slot and is masked
                 // out of the syndrome.  Otherwise edges k >= d are masked.
-                uint32_t xb[DC], a[DC];
+                uint32_t xb[DC];
+                float a[DC];
 #pragma unroll
                 for (int k = 0; k < DC; ++k) {
                     const bool valid = RX || k < d;
-                    xb[k] = __float_as_uint(sv[k][q] - eprev[r][k][q]);
-                    a[k] = valid ? (xb[k] & 0x7fffffffu) : 0x7f800000u;
+                    const float x = sv[k][q] - eprev[r][k][q];
+                    xb[k] = __float_as_uint(x);
+                    a[k] = valid ? fabsf(x) : __builtin_inff();
                 }
-                uint32_t mn0 = a[0], mn1 = 0x7f800000u;
-#pragma unroll
-                for (int k = 1; k < DC; ++k) {
-                    mn1 = min(mn1, max(mn0, a[k]));
-                    mn0 = min(mn0, a[k]);
-                }
-                uint32_t par = 0, syn = 0;
+                float mn0, mn1;
+                min_pair<DC>(a, mn0, mn1);
+                uint32_t pv[DC], sb[DC];
 #pragma unroll
                 for (int k = 0; k < DC; ++k) {
                     const bool valid = RX || k < d;
-                    par ^= valid ? xb[k] : 0u;
-                    syn ^= valid ? __float_as_uint(sv[k][q]) : 0u;
+                    pv[k] = valid ? xb[k] : 0u;
+                    sb[k] = valid ? __float_as_uint(sv[k][q]) : 0u;
                 }
+                uint32_t par = xor_all<DC>(pv), syn = xor_all<DC>(sb);
                 if (RX && !rowv) syn = 0u;
                 umask |= (syn >> 31) << q;
-                uint32_t b0 = mn0, b1 = mn1;
-                if (alpha != nullptr && tt[q] <= L && rowv) {
-                    const float al = alpha[(tt[q] - 1) * ncls + rcls[r]], be = beta[(tt[q] - 1) * ncls + rcls[r]];
-                    const float v0 = fmaf(al, __uint_as_float(mn0), -be), v1 = fmaf(al, __uint_as_float(mn1), -be);
-                    b0 = __float_as_uint(v0 > 0.0f ? v0 : 0.0f);
-                    b1 = __float_as_uint(v1 > 0.0f ? v1 : 0.0f);
+                uint32_t b0 = __float_as_uint(mn0), b1 = __float_as_uint(mn1);
+                if (alpha != nullptr) {
+                    if (tt[q] <= L && rowv) {
+                        const float al = alpha[(tt[q] - 1) * ncls + rcls[r]];
+                        const float be = beta[(tt[q] - 1) * ncls + rcls[r]];
+                        const float v0 = fmaf(al, mn0, -be), v1 = fmaf(al, mn1, -be);
+                        b0 = __float_as_uint(v0 > 0.0f ? v0 : 0.0f);
+                        b1 = __float_as_uint(v1 > 0.0f ? v1 : 0.0f);
+                    }
                 }
                 // the row's sign parity folded into both magnitudes; each edge
-                // then XORs in its own sign bit
+                // then XORs in its own sign bit.  The empty asm keeps the
+                // compiler from moving the parity XOR back onto every edge.
                 const uint32_t sg = par & 0x80000000u;
-                const uint32_t b0s = b0 ^ sg, b1s = b1 ^ sg;
+                uint32_t b0s = b0 ^ sg, b1s = b1 ^ sg;
+                asm("" : "+v"(b0s), "+v"(b1s));
 #pragma unroll
                 for (int k = 0; k < DC; ++k)
                     eprev[r][k][q] = __uint_as_float(((a[k] == mn0) ? b1s : b0s) ^ (xb[k] & 0x80000000u));
@@ -247,7 +318,7 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
         for (int q = 0; q < kF; ++q) wm |= (__ballot((umask >> q) & 1u) != 0ull ? 1u : 0u) << q;
         if ((tid & 63) == 0 && wm) atomicOr(&sh->red[p], wm);
         __syncthreads();
-        const uint32_t U = sh->red[p];
+        const uint32_t U = __builtin_amdgcn_readfirstlane(sh->red[p]);
         if (tid == 0) sh->red[p ^ 1] = 0u;
 
         // ---- decisions, outputs, refills --------------------------------------
@@ -272,7 +343,7 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
                 iters[f] = (early && clean) ? tt[q] - 1 : L;
                 if (ok) ok[f] = clean ? 1 : 0;
             }
-            const int32_t nf = sh->next[q][gen[q] & 1];
+            const int32_t nf = __builtin_amdgcn_readfirstlane(sh->next[q][gen[q] & 1]);
             if (tid == 0) sh->next[q][(gen[q] + 1) & 1] = (int32_t)atomicAdd(queue, 1u);
             fr[q] = nf;
             gen[q] += 1;
@@ -282,21 +353,25 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
                 for (int k = 0; k < DC; ++k) eprev[r][k][q] = 0.0f;
         }
 
+        fin = __builtin_amdgcn_readfirstlane(fin);
+
         // ---- bit pass -------------------------------------------------------------
 #pragma unroll
         for (int c = 0; c < CPT; ++c) {
             const int32_t j = tid + c * nt;
             if (j < n) {
-                const uint32_t base = eta0 + (uint32_t)sizeof(vf2) * (ckd[c] & 0xffffu);
-                const int32_t dv = (int32_t)(ckd[c] >> 16);
+                // CX: every bit has DV slots, so bit j's first slot is DV j
+                const uint32_t base =
+                    eta0 + (uint32_t)sizeof(vf2) * (CX ? (uint32_t)(DV * j) : (ckd[c] & 0xffffu));
+                const int32_t dv = CX ? DV : (int32_t)(ckd[c] >> 16);
                 vf2 ev[DV];
 #pragma unroll
                 for (int k = 0; k < DV; ++k)
                     ev[k] = lds_ld(lds, base + (uint32_t)sizeof(vf2) * (uint32_t)(CX || k < dv ? k : 0));
-                vf2 acc = vf2{0.0f, 0.0f};
+                vf2 acc = (CX || 0 < dv) ? ev[0] : vf2{0.0f, 0.0f};
 #pragma unroll
-                for (int k = 0; k < DV; ++k)
-                    acc = acc + ((CX || k < dv) ? ev[k] : vf2{0.0f, 0.0f}); // +0 adds are exact
+                for (int k = 1; k < DV; ++k)
+                    acc = acc + ((CX || k < dv) ? ev[k] : vf2{0.0f, 0.0f}); // +0 adds change no s
                 vf2 sn = acc + rc[c];
 #pragma unroll
                 for (int q = 0; q < kF; ++q) {
@@ -327,7 +402,7 @@ struct Variant {
 };
 
 // Exact-degree variants for the regular codes in use first, then masked ones.
-// The order is the dispatch order of run_variant below.
+// The order is the dispatch order of pick below.
 constexpr Variant kVariants[] = {
     {6, true, 3, true, 2, 4},   {6, true, 8, false, 2, 4},  {9, true, 8, false, 2, 8},   {12, true, 8, false, 1, 4},
     {16, true, 8, false, 1, 8}, {8, false, 8, false, 2, 4}, {16, false, 16, false, 1, 8}, {6, true, 3, true, 1, 4},
@@ -339,19 +414,6 @@ template <int V> __device__ __forceinline__ void run_v(const Job &J, int32_t L, 
     run_onchip<v.dc, v.rx, v.dv, v.cx, v.rpt, v.cpt>(J, L, early, lds);
 }
 
-__device__ __forceinline__ void run_variant(const Job &J, int32_t L, int32_t early, unsigned char *lds) {
-    switch (J.variant) {
-    case 0: run_v<0>(J, L, early, lds); break;
-    case 1: run_v<1>(J, L, early, lds); break;
-    case 2: run_v<2>(J, L, early, lds); break;
-    case 3: run_v<3>(J, L, early, lds); break;
-    case 4: run_v<4>(J, L, early, lds); break;
-    case 5: run_v<5>(J, L, early, lds); break;
-    case 6: run_v<6>(J, L, early, lds); break;
-    default: run_v<7>(J, L, early, lds); break;
-    }
-}
-static_assert(kNumVariants == 8, "run_variant dispatches eight variants");
 
 // One graph per launch, one variant instantiated.  W > 0 asks the compiler
 // for at least W waves per SIMD (fewer registers per thread, more resident
@@ -371,10 +433,26 @@ struct JobTable {
     int32_t njobs;
     Job job[kMaxJobs];
 };
+// The widest masked variant is left out of the multi-code kernel: the
+// register demand of a kernel is that of its largest variant, and that one
+// alone would push every variant of the launch into spills.  Jobs that need
+// it get a launch of their own.
+constexpr int kWideVariant = 6;
+static_assert(kNumVariants == 8, "k_onchip_multi dispatches variants 0-5 and 7");
+
 __global__ __launch_bounds__(kMaxThreads) void k_onchip_multi(const JobTable jt, int32_t L, int32_t early) {
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
     for (int32_t c = 0; c < jt.njobs; ++c) {
-        run_variant(jt.job[c], L, early, lds);
+        switch (jt.job[c].variant) {
+        case 0: run_v<0>(jt.job[c], L, early, lds); break;
+        case 1: run_v<1>(jt.job[c], L, early, lds); break;
+        case 2: run_v<2>(jt.job[c], L, early, lds); break;
+        case 3: run_v<3>(jt.job[c], L, early, lds); break;
+        case 4: run_v<4>(jt.job[c], L, early, lds); break;
+        case 5: run_v<5>(jt.job[c], L, early, lds); break;
+        case 7: run_v<7>(jt.job[c], L, early, lds); break;
+        default: break; // the host never places kWideVariant here
+        }
         __syncthreads();
     }
 }
@@ -512,27 +590,53 @@ int onchip_decode_multi(const ldpc_job *jobs, int32_t njobs, int32_t L, uint32_t
     int64_t frames = 0;
     int num_cu = 0;
     uint32_t *queues = (uint32_t *)ws;
+    std::vector<std::pair<Job, const ldpc_graph *>> wide; // jobs with a launch of their own
+    int32_t nj = 0;
     for (int32_t k = 0; k < njobs; ++k) {
         const ldpc_job &jb = jobs[order[k]];
         const ldpc_graph &g = *jb.g;
         if (!onchip_fits(g)) return LDPC_EUNSUPPORTED;
-        const int v = pick(g);
+        int v = pick(g);
+        if (v == kWideVariant) // another variant that fits keeps the job in the shared launch
+            for (int c = 0; c < kNumVariants; ++c)
+                if (c != kWideVariant && variant_ok(g, c)) {
+                    v = c;
+                    break;
+                }
+        const Job J = make_job(g, v, jb.llr_dev, jb.B, jb.bits_dev, jb.post_dev, jb.iters_dev, jb.ok_dev, nullptr,
+                               nullptr, queues + k);
+        if (v == kWideVariant) {
+            if (jb.B > 0) wide.emplace_back(J, &g);
+            continue;
+        }
         const int t = threads_for(g, kVariants[v]);
         threads = t > threads ? t : threads;
         lds = onchip_lds_bytes(g) > lds ? onchip_lds_bytes(g) : lds;
         frames += jb.B;
         num_cu = g.num_cu;
-        jt.job[k] = make_job(g, v, jb.llr_dev, jb.B, jb.bits_dev, jb.post_dev, jb.iters_dev, jb.ok_dev, nullptr,
-                             nullptr, queues + k);
+        jt.job[nj++] = J;
     }
-    jt.njobs = njobs;
-    if (frames == 0) return LDPC_OK;
-    int grid = 0;
-    int st = launch_grid((const void *)k_onchip_multi, threads, lds, num_cu, frames, 0, &grid);
-    if (st) return st;
+    jt.njobs = nj;
     const int32_t early = (flags & LDPC_NO_EARLY_EXIT) ? 0 : 1;
+    if (frames == 0 && wide.empty()) return LDPC_OK;
     k_zero_words<<<1, 64, 0, stream>>>(queues, njobs);
-    timed_launch(K_ONCHIP, stream, [&] { k_onchip_multi<<<grid, threads, lds, stream>>>(jt, L, early); });
+    if (frames > 0) {
+        int grid = 0;
+        const int st = launch_grid((const void *)k_onchip_multi, threads, lds, num_cu, frames, 0, &grid);
+        if (st) return st;
+        timed_launch(K_ONCHIP, stream, [&] { k_onchip_multi<<<grid, threads, lds, stream>>>(jt, L, early); });
+    }
+    for (const auto &w : wide) {
+        const ldpc_graph &g = *w.second;
+        const KernelFn fn = kKernels[0][kWideVariant];
+        const int t = threads_for(g, kVariants[kWideVariant]);
+        const size_t l = onchip_lds_bytes(g);
+        int grid = 0;
+        const int st = launch_grid((const void *)fn, t, l, g.num_cu, w.first.B, 0, &grid);
+        if (st) return st;
+        const Job J = w.first;
+        timed_launch(K_ONCHIP, stream, [&] { fn<<<grid, t, l, stream>>>(J, L, early); });
+    }
     return hipGetLastError() == hipSuccess ? LDPC_OK : LDPC_EHIP;
 }
 

@@ -168,6 +168,69 @@ __global__ __launch_bounds__(512) void k_check(const int32_t *__restrict__ row_p
     if (act && syn) unsat[f] = 1u;
 }
 
+// The same check update for graphs whose rows all have DC edges: the loop is
+// unrolled and every load of the row is issued before any use, so a
+// wavefront keeps 2 DC memory requests in flight.
+template <int DC>
+__global__ __launch_bounds__(512) void k_check_dc(const int32_t *__restrict__ col_idx,
+                                                  const int32_t *__restrict__ row_class, int32_t m, int32_t n,
+                                                  int64_t E, int32_t row_blocks, const float *__restrict__ r,
+                                                  const float *__restrict__ s, float *__restrict__ eta,
+                                                  const uint32_t *__restrict__ done, uint32_t *__restrict__ unsat,
+                                                  int32_t t, const float *__restrict__ alpha,
+                                                  const float *__restrict__ beta, int32_t n_classes) {
+    const uint32_t bid = xcd_swizzle(blockIdx.x, gridDim.x);
+    const int32_t tile = bid / row_blocks;
+    const int32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int32_t row = (bid % row_blocks) * (int32_t)(blockDim.x >> 6) + w;
+    const int lane = threadIdx.x & 63;
+    const int32_t f = tile * kTile + lane;
+    const bool act = !done[f];
+    if (row >= m || !__any(act)) return;
+
+    const float *sv = (t == 1 ? r : s) + (size_t)tile * n * kTile + lane;
+    float *et = eta + (size_t)tile * E * kTile + lane;
+    const int64_t e0 = (int64_t)row * DC; // rows of equal degree: CSR offsets are row * DC
+    float sj[DC], ev[DC];
+#pragma unroll
+    for (int k = 0; k < DC; ++k) sj[k] = sv[(size_t)col_idx[e0 + k] * kTile];
+#pragma unroll
+    for (int k = 0; k < DC; ++k) ev[k] = (t == 1) ? 0.0f : et[(size_t)(e0 + k) * kTile];
+    float x[DC];
+    float min0 = __builtin_inff(), min1 = __builtin_inff();
+    int32_t am = -1;
+    uint32_t par = 0, syn = 0;
+#pragma unroll
+    for (int k = 0; k < DC; ++k) {
+        syn ^= sj[k] < 0.0f;
+        x[k] = (t == 1) ? sj[k] : sj[k] - ev[k];
+        const float a = fabsf(x[k]);
+        par ^= x[k] < 0.0f;
+        if (a < min0) {
+            min1 = min0;
+            min0 = a;
+            am = k;
+        } else if (a < min1) {
+            min1 = a;
+        }
+    }
+    if (alpha != nullptr) {
+        const int32_t c = row_class[row];
+        const float al = alpha[(t - 1) * n_classes + c], be = beta[(t - 1) * n_classes + c];
+        const float v0 = fmaf(al, min0, -be), v1 = fmaf(al, min1, -be);
+        min0 = v0 > 0.0f ? v0 : 0.0f;
+        min1 = v1 > 0.0f ? v1 : 0.0f;
+    }
+    if (act) {
+#pragma unroll
+        for (int k = 0; k < DC; ++k) {
+            const float mag = (k == am) ? min1 : min0;
+            et[(size_t)(e0 + k) * kTile] = (par ^ (x[k] < 0.0f ? 1u : 0u)) ? -mag : mag;
+        }
+        if (syn) unsat[f] = 1u;
+    }
+}
+
 // One wavefront = one bit column x one frame tile.
 __global__ __launch_bounds__(512) void k_bit(const int32_t *__restrict__ col_ptr, const int32_t *__restrict__ csc_edge,
                                              int32_t n, int64_t E, int32_t col_blocks, const float *__restrict__ r,
@@ -286,14 +349,25 @@ int stream_decode(const ldpc_graph &g, const float *llr, int32_t B, int32_t L, u
     const int32_t col_blocks = (g.n + waves - 1) / waves;
     const int32_t nchunks = (g.n + 63) / 64;
     const int32_t ncls = (int32_t)g.class_degrees.size();
+    // unrolled check kernel when every row has 6 or 7 edges
+    const int32_t regular = (g.dc_min == g.dc_max && (g.dc_max == 6 || g.dc_max == 7)) ? g.dc_max : 0;
 
     k_flags_init<<<(frames + 255) / 256, 256, 0, stream>>>(B, frames, w.done, w.unsat[0], w.unsat[1], w.conv);
     k_to_tiles<<<nt * nchunks, 256, 0, stream>>>(llr, B, g.n, w.r);
     for (int32_t t = 1; t <= L; ++t) {
         timed_launch(K_CHECK, stream, [&] {
-            k_check<<<nt * row_blocks, 64 * waves, 0, stream>>>(g.row_ptr, g.col_idx, g.row_class, g.m, g.n, g.E, B,
-                                                         row_blocks, w.r, w.s, w.eta, w.done, w.unsat[t & 1], t,
-                                                         alpha, beta, ncls);
+            if (regular == 6)
+                k_check_dc<6><<<nt * row_blocks, 64 * waves, 0, stream>>>(g.col_idx, g.row_class, g.m, g.n, g.E,
+                                                                          row_blocks, w.r, w.s, w.eta, w.done,
+                                                                          w.unsat[t & 1], t, alpha, beta, ncls);
+            else if (regular == 7)
+                k_check_dc<7><<<nt * row_blocks, 64 * waves, 0, stream>>>(g.col_idx, g.row_class, g.m, g.n, g.E,
+                                                                          row_blocks, w.r, w.s, w.eta, w.done,
+                                                                          w.unsat[t & 1], t, alpha, beta, ncls);
+            else
+                k_check<<<nt * row_blocks, 64 * waves, 0, stream>>>(g.row_ptr, g.col_idx, g.row_class, g.m, g.n,
+                                                                    g.E, B, row_blocks, w.r, w.s, w.eta, w.done,
+                                                                    w.unsat[t & 1], t, alpha, beta, ncls);
         });
         timed_launch(K_BIT, stream, [&] {
             k_bit<<<nt * col_blocks, 64 * waves, 0, stream>>>(g.col_ptr, g.csc_edge, g.n, g.E, col_blocks, w.r, w.s, w.eta,

@@ -3,15 +3,16 @@ compare it with plain Min-Sum at equal frame error rate.
 
     python -m paper_2507_10424_amd.train_nms --steps 2000 --out weights.npz
 
-Recipe: the (3,6)-regular n=1024 code (seed 2), T = 10 unrolled iterations,
+Recipe: the (3,6)-regular n=1024 code (seed 2; `--code qc64800` takes the
+irregular QC code n = 64800 of the same package instead), T = 10 unrolled iterations,
 per-iteration per-check-degree scale and offset initialised to 1 and 0,
 4096 fresh all-zero frames per step with Eb/N0 drawn per frame uniformly
 from [1, 3] dB, checkpoints every 2 iterations, Adam (lr 1e-2).  Evaluation:
 fresh frames at 2 dB decoded by plain Min-Sum (at most 50 iterations) and by
 the learned decoder (at most T iterations), both with per-frame early exit,
 until plain Min-Sum has made at least `--min-errors` frame errors; FER with
-Wilson 95% intervals, mean iterations and decoded Gbit/s of each.
-Prints one JSON line.
+Wilson 95% intervals, mean iterations and decoded Gbit/s of each, at every
+`--eval-ebn0` point.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -84,7 +85,9 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=1e-2)
     ap.add_argument("--ebn0-lo", type=float, default=1.0)
     ap.add_argument("--ebn0-hi", type=float, default=3.0)
-    ap.add_argument("--eval-ebn0", type=float, default=2.0)
+    ap.add_argument("--code", default="regular1024", choices=["regular1024", "qc64800"])
+    ap.add_argument("--eval-ebn0", type=float, nargs="+", default=[2.0])
+    ap.add_argument("--max-eval-frames", type=int, default=2_000_000)
     ap.add_argument("--eval-batch", type=int, default=65536)
     ap.add_argument("--min-errors", type=int, default=100)
     ap.add_argument("--seed", type=int, default=1234)
@@ -100,7 +103,10 @@ def main(argv=None):
         print(msg, file=sys.stderr, flush=True)
 
     dev = torch.device("cuda:0")
-    H = wl.regular_ldpc(1024, 512, 3, 6, seed=2)
+    if args.code == "qc64800":
+        H, code_name = wl.large_qc_code(seed=5), "irregular QC n=64800 m=32400 Z=360"
+    else:
+        H, code_name = wl.regular_ldpc(1024, 512, 3, 6, seed=2), "(3,6)-regular n=1024 m=512"
     g = ldpc.build_graph(torch.from_numpy(H).to(dev))
     tr = NMSTrainer(g, T=args.T, batch=args.batch, ckpt_every=args.ckpt_every,
                     ebn0_range=(args.ebn0_lo, args.ebn0_hi), lr=args.lr, seed=args.seed)
@@ -116,10 +122,10 @@ def main(argv=None):
     if args.out:
         sd = tr.state_dict()
         np.savez(args.out, **{k: (v.numpy() if torch.is_tensor(v) else np.asarray(v)) for k, v in sd.items()})
-    res = evaluate(g, tr.alpha, tr.beta, args.T, args.eval_ebn0, batch=args.eval_batch,
-                   min_errors=args.min_errors, log=log)
+    res = [evaluate(g, tr.alpha, tr.beta, args.T, eb, batch=args.eval_batch, min_errors=args.min_errors,
+                    max_frames=args.max_eval_frames, log=log) for eb in args.eval_ebn0]
     hist = torch.stack(tr.history).cpu().numpy() if tr.history else np.zeros(1)
-    line = {"metric": "neural vs plain Min-Sum at equal FER", "code": "(3,6)-regular n=1024 m=512",
+    line = {"metric": "neural vs plain Min-Sum at equal FER", "code": code_name,
             "T": args.T, "train_steps": tr.steps, "train_batch": args.batch, "train_seconds": round(train_s, 2),
             "loss_first": float(hist[: min(10, hist.size)].mean()), "loss_last": float(hist[-10:].mean()),
             "alpha": tr.alpha.cpu().numpy().ravel().round(4).tolist(),

@@ -58,3 +58,30 @@ def test_multi_mixed_sizes_and_empty_job(tdev):
         if llr.shape[0] == 0:
             continue
         assert_parity(tuple(t.cpu().numpy() for t in o), oracle_decode(H, llr, 30), f"mixed {k}")
+
+
+def test_multi_with_wide_variant_job(tdev):
+    """A code with bit degree above 8 needs the widest masked kernel variant,
+    which runs in a launch of its own next to the shared multi-code launch."""
+    torch, dev = tdev
+    from paper_2507_10424_amd import ldpc
+    wide = wl.random_irregular_code(400, 160, seed=11, dv_choices=(2, 3, 12), max_row_degree=16)
+    assert wide.sum(axis=0).max() > 8
+    codes = [wl.regular_ldpc(96, 48, 3, 6, seed=1), wide, wl.regular_ldpc(1024, 512, 3, 6, seed=2)]
+    Bs = [300, 257, 129]
+    jobs, inputs = [], []
+    for k, (H, B) in enumerate(zip(codes, Bs)):
+        llr = np.random.default_rng(40 + k).normal(1.0, 1.3, size=(B, H.shape[1])).astype(np.float32)
+        g = ldpc.build_graph(torch.from_numpy(H).to(dev))
+        jobs.append((g, torch.from_numpy(llr).to(dev)))
+        inputs.append((H, llr))
+    outs = ldpc.minsum_decode_multi(jobs, 40)
+    torch.cuda.synchronize()
+    for k, ((H, llr), o, (g, lt)) in enumerate(zip(inputs, outs, jobs)):
+        got = tuple(t.cpu().numpy() for t in o)
+        note(f"[multi-wide] code {k}: n={H.shape[1]} B={llr.shape[0]} mean iters {got[2].mean():.2f}")
+        assert_parity(got, oracle_decode(H, llr, 40), f"multi wide {k}")
+        single = ldpc.minsum_decode(g, lt, 40)
+        torch.cuda.synchronize()
+        for x, y in zip(o, single):
+            assert torch.equal(x, y)
