@@ -74,9 +74,14 @@ def parse():
     ap.add_argument("--config", default="regular1024", choices=["regular1024", "qc64800", "regular96", "multi8"])
     ap.add_argument("--no-autotune", action="store_true", help="skip the autotuner (library defaults)")
     ap.add_argument("--path", default="auto", choices=["auto", "stream", "onchip"])
+    ap.add_argument("--check-period", type=int, default=1,
+                    help="codeword test after every k-th iteration (the paper's GPU runs use 6)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-nms", action="store_true", help="skip the learned-decoder comparison")
     ap.add_argument("--profile-only", action="store_true", help="warmup + timed steps, no extras (for rocprofv3)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy 256 MiB three times (calibrates the HBM byte counters of a profiler)")
     return ap.parse_args()
 
 
@@ -86,7 +91,7 @@ def workload(name):
         H = wl.regular_ldpc(1024, 512, 3, 6, seed=2)
         return dict(name="(3,6)-regular n=1024 m=512, 65536 random codewords x 7 Eb/N0 points 1.0..4.0 dB, "
                          "L=50, early exit", H=H, batch=65536, ebn0=[1.0, 1.5, 2.0, 2.5, 3.0, 3.5, 4.0],
-                    L=50, rate=0.5, random_cw=True, seed_cw=200, seed_noise=300)
+                    L=50, rate=0.5, random_cw=True, seed_cw=200, seed_noise=300, nms_points=[1, 2, 3])
     if name == "qc64800":
         H = wl.large_qc_code(seed=5)
         return dict(name="irregular QC n=64800 m=32400 Z=360, 4096 all-zero frames x Eb/N0 1.0..1.6 dB, L=50, "
@@ -109,6 +114,14 @@ def main():
               "by running one independent process per GPU, which this build does not launch", file=sys.stderr)
         sys.exit(2)
     import torch
+    if args.copy_probe:
+        x = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda:0")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read_per_launch": x.numel() * 4, "launches": 3}), flush=True)
+        return
     from paper_2507_10424_amd import ldpc
     from paper_2507_10424_amd import workloads as wl
 
@@ -127,6 +140,8 @@ def main():
     m, n = H.shape
     B, L = W["batch"], W["L"]
     flags = {"auto": 0, "stream": ldpc.LDPC_FORCE_STREAM, "onchip": ldpc.LDPC_FORCE_ONCHIP}[args.path]
+    if args.check_period != 1:
+        flags |= ldpc.check_period(args.check_period)
     log(f"[bench] workload: {W['name']}")
     t0 = time.time()
     g = ldpc.build_graph(torch.from_numpy(H).to(dev))
@@ -245,7 +260,7 @@ def main():
         per = max(4, min(B, int(args.cpu_seconds * nthreads / max(t_probe, 1e-6) / len(llrs))))
         sample = [x[:per].cpu().numpy() for x in llrs]
         tc = time.time()
-        ref = [oracle.minsum_decode(H, x, L, nthreads=nthreads) for x in sample]
+        ref = [oracle.minsum_decode(H, x, L, nthreads=nthreads, check_period=args.check_period) for x in sample]
         t_cpu = time.time() - tc
         cpu_frames = per * len(sample)
         cpu = {"value": round(cpu_frames * n / t_cpu / 1e9, 6), "unit": "Gbit/s", "cores": nthreads,
@@ -259,18 +274,77 @@ def main():
             mism += int(np.any(gb != ob, axis=1).sum()) + int((gi != oi).sum())
         cpu["gpu_mismatches_on_sample"] = mism
 
+    nms = None if args.no_nms else nms_vs_plain(args, W, g, llrs, cws, flags, ws)
+
     line = {
         "metric": "coded Gbit/s & edge-msg/s (% HBM BW); neural vs plain Min-Sum at equal FER",
         "value": round(gbits, 3), "unit": "Gbit/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": W["name"], "n": n, "m": m, "edges": E, "batch": B, "batches_per_step": len(llrs),
-                   "ebn0_db": W["ebn0"], "max_iter": L, "path": args.path, "tuning": tuning},
+                   "ebn0_db": W["ebn0"], "max_iter": L, "path": args.path, "check_period": args.check_period,
+                   "tuning": tuning},
         "edge_msg_per_s": edge_msgs, "info_gbit_s": round(gbits * k_info / n, 3) if k_info else None,
         "mean_iters": round(tot_iters / frames_step, 3), "per_point": per_point,
-        "roofline": roofline, "cpu_baseline": cpu,
+        "roofline": roofline, "cpu_baseline": cpu, "nms_vs_plain": nms,
     }
     print(json.dumps(line), flush=True)
+
+
+def wilson(k: int, n: int, z: float = 1.96):
+    if n == 0:
+        return [0.0, 1.0]
+    p = k / n
+    d = 1 + z * z / n
+    c = (p + z * z / (2 * n)) / d
+    h = z * (p * (1 - p) / n + z * z / (4 * n * n)) ** 0.5 / d
+    return [round(max(0.0, c - h), 6), round(min(1.0, c + h), 6)]
+
+
+def nms_vs_plain(args, W, g, llrs, cws, flags, ws):
+    """The learned decoder (T iterations, weights trained by train_nms.py and
+    stored in the package) against plain Min-Sum (L iterations) on the same
+    frames: FER with Wilson 95% intervals and coded Gbit/s of each."""
+    import torch
+    from paper_2507_10424_amd import ldpc
+    path = os.path.join(ROOT, "paper_2507_10424_amd", "weights", f"nms_{args.config}.json")
+    if not os.path.exists(path):
+        log(f"[bench] no learned weights at {path}; skipping the learned decoder")
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    dev = llrs[0].device
+    alpha = torch.tensor(rec["alpha"], dtype=torch.float32, device=dev)
+    beta = torch.tensor(rec["beta"], dtype=torch.float32, device=dev)
+    T, L = int(rec["T"]), W["L"]
+    points = W.get("nms_points", list(range(len(llrs))))
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    res = []
+    for p in points:
+        x, cw = llrs[p], cws[p]
+        B, n = x.shape
+        row = {"ebn0_db": W["ebn0"][p], "frames": B}
+        for name, fn in (("plain", lambda: ldpc.minsum_decode(g, x, L, flags=flags, want_post=False, workspace=ws)),
+                         ("learned", lambda: ldpc.nms_decode(g, x, T, alpha, beta, flags=flags, want_post=False,
+                                                             workspace=ws))):
+            fn()  # warm-up
+            torch.cuda.synchronize()
+            ev0.record()
+            out = fn()
+            ev1.record()
+            torch.cuda.synchronize()
+            ms = ev0.elapsed_time(ev1)
+            ref = cw if cw is not None else torch.zeros_like(out[0])
+            fe = int((out[0] != ref).any(dim=1).sum())
+            row[name] = {"max_iter": L if name == "plain" else T, "fer": fe / B, "fer_ci95": wilson(fe, B),
+                         "mean_iters": round(float(out[2].float().mean()), 3),
+                         "coded_gbit_s": round(B * n / (ms * 1e-3) / 1e9, 3)}
+        lo_p, hi_p = row["plain"]["fer_ci95"]
+        lo_l, hi_l = row["learned"]["fer_ci95"]
+        row["fer_intervals_overlap"] = bool(lo_l <= hi_p and lo_p <= hi_l)
+        row["speedup"] = round(row["learned"]["coded_gbit_s"] / row["plain"]["coded_gbit_s"], 3)
+        res.append(row)
+    return {"weights": os.path.relpath(path, ROOT), "T": T, "train": rec.get("train"), "points": res}
 
 
 def bench_multi(args, W, dev, lib):
@@ -323,7 +397,7 @@ def bench_multi(args, W, dev, lib):
         fe = int((o[0] != 0).any(dim=1).sum())
         per_code.append(dict(n=c["n"], rate=round(c["rate"], 4), Z=c["Z"], batch=c["batch"], fer=fe / c["batch"],
                              mean_iters=round(float(o[2].float().mean()), 3)))
-    ops = 12.0 * edges_iters
+    ops = float(sum(alu_ops_per_frame_iter(c["H"]) * int(o[2].to(torch.int64).sum()) for c, o in zip(fam, outs)))
     achieved = ops / (ms_multi * 1e-3) / 1e12
     line = {
         "metric": "coded Gbit/s & edge-msg/s (% HBM BW); neural vs plain Min-Sum at equal FER",

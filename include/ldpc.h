@@ -56,6 +56,14 @@ enum ldpc_flags {
     LDPC_FORCE_ONCHIP = 1u << 2
 };
 
+/* Codeword-test period (the paper's termination variant, Sec. IV: its GPU
+ * decoder tests for a codeword after every 6th iteration).  With early exit a
+ * frame is tested before the first iteration and after every k-th one, and
+ * stops at the first test it passes.  k sits in bits 8..15 of the flags;
+ * 0 and 1 both test after every iteration.  Other flag bits must be 0. */
+#define LDPC_CHECK_PERIOD_SHIFT 8
+#define LDPC_CHECK_PERIOD(k) ((((uint32_t)(k)) & 0xffu) << LDPC_CHECK_PERIOD_SHIFT)
+
 /*
  * Build the Tanner graph of H (Sec. II-B: the neighbour sets N_i of each check
  * row and M_j of each bit column) on the device.
@@ -107,7 +115,8 @@ size_t ldpc_decode_workspace_bytes(const ldpc_graph *g, int32_t B, uint32_t flag
  *   post_dev  B x n float32 out, may be NULL: posterior LLRs s_j.
  *   iters_dev B int32 out: 0 if the channel decision is a codeword, else the
  *             first iteration t after which the syndrome is zero, else L.
- *             With LDPC_NO_EARLY_EXIT always L.
+ *             With LDPC_NO_EARLY_EXIT always L.  With a check period k > 1
+ *             only multiples of k are tested (t = 0, k, 2k, ...).
  *   ok_dev    B uint8 out, may be NULL: 1 iff the final decision is a codeword.
  *   ws_dev, ws_bytes  workspace of at least ldpc_decode_workspace_bytes(g, B,
  *             flags) bytes, 256-byte aligned; its contents need not be set.
@@ -120,7 +129,8 @@ size_t ldpc_decode_workspace_bytes(const ldpc_graph *g, int32_t B, uint32_t flag
  * outputs are those of the iteration at which it stopped.  All arithmetic is
  * IEEE binary32 with round-to-nearest-even and no contraction.
  * Errors: LDPC_EINVAL (null g / llr / bits / iters with B > 0, B < 0,
- * max_iter < 0), LDPC_EWORKSPACE, LDPC_EUNSUPPORTED, LDPC_EHIP.
+ * max_iter < 0, an unknown flag bit), LDPC_EWORKSPACE, LDPC_EUNSUPPORTED,
+ * LDPC_EHIP.
  */
 int ldpc_minsum_decode(const ldpc_graph *g, const float *llr_dev, int32_t B, int32_t max_iter,
                        uint32_t flags, uint8_t *bits_dev, float *post_dev, int32_t *iters_dev,

@@ -29,6 +29,13 @@ def build_oracle(mutant: int = 0, out: str | None = None) -> str:
     return out
 
 
+def _period(early_exit, check_period):
+    k = int(check_period)
+    if k < 1:
+        raise ValueError("check_period must be >= 1")
+    return k if early_exit else 0
+
+
 def _p(a, t):
     return None if a is None else a.ctypes.data_as(t)
 
@@ -55,9 +62,11 @@ class Oracle:
         self.lib = lib
         self.path = path
 
-    def minsum_decode(self, H, llr, max_iter, early_exit=True, nthreads=0):
+    def minsum_decode(self, H, llr, max_iter, early_exit=True, nthreads=0, check_period=1):
         """Algorithm 1 on every frame of ``llr`` (B, n).  Returns
-        (bits uint8 (B,n), post float32 (B,n), iters int32 (B,), ok uint8 (B,))."""
+        (bits uint8 (B,n), post float32 (B,n), iters int32 (B,), ok uint8 (B,)).
+        With early exit the codeword test runs before the first iteration and
+        after every ``check_period``-th one."""
         H = np.ascontiguousarray(H, dtype=np.uint8)
         llr = np.ascontiguousarray(llr, dtype=np.float32)
         m, n = H.shape
@@ -68,13 +77,13 @@ class Oracle:
         iters = np.empty(B, np.int32)
         ok = np.empty(B, np.uint8)
         st = self.lib.oracle_minsum_decode(_p(H, _u8p), m, n, _p(llr, _f32p), B, int(max_iter),
-                                           int(bool(early_exit)), _p(bits, _u8p), _p(post, _f32p),
+                                           _period(early_exit, check_period), _p(bits, _u8p), _p(post, _f32p),
                                            _p(iters, _i32p), _p(ok, _u8p), int(nthreads))
         if st:
             raise ValueError(f"oracle_minsum_decode status {st}")
         return bits, post, iters, ok
 
-    def nms_decode(self, H, llr, max_iter, alpha, beta, early_exit=True, nthreads=0):
+    def nms_decode(self, H, llr, max_iter, alpha, beta, early_exit=True, nthreads=0, check_period=1):
         H = np.ascontiguousarray(H, dtype=np.uint8)
         llr = np.ascontiguousarray(llr, dtype=np.float32)
         alpha = np.ascontiguousarray(alpha, dtype=np.float32)
@@ -88,7 +97,7 @@ class Oracle:
         iters = np.empty(B, np.int32)
         ok = np.empty(B, np.uint8)
         st = self.lib.oracle_nms_decode(_p(H, _u8p), m, n, _p(llr, _f32p), B, int(max_iter),
-                                        int(bool(early_exit)), _p(alpha, _f32p), _p(beta, _f32p), T, C,
+                                        _period(early_exit, check_period), _p(alpha, _f32p), _p(beta, _f32p), T, C,
                                         _p(bits, _u8p), _p(post, _f32p), _p(iters, _i32p), _p(ok, _u8p),
                                         int(nthreads))
         if st:

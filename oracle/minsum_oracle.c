@@ -16,6 +16,9 @@
  *     eq. lambda_j, the slicer of eq. slice and the GF(2) syndrome H b = 0;
  *   - the pre-loop codeword test of the paper's kernel listing (Sec. IV), so
  *     a channel decision that is already a codeword stops with 0 iterations;
+ *   - the paper's own termination variant (Sec. IV, the GPU experiments and
+ *     the kernel-profile table): the codeword test runs only after every
+ *     k-th iteration (k = 6 there); k = 1 tests after every iteration;
  *   - Algorithm 2 (map-reduce form, Sec. III) on dense m x n arrays, for the
  *     reformulation check only;
  *   - an optional normalised/offset check update (learned per-iteration,
@@ -242,11 +245,12 @@ static void decode_frame(const tanner_t *g, const float *r, int32_t L, int early
 #else
     int skip_zero = 0;
 #endif
+    /* early = the codeword-test period k (0: never test, run all L iterations) */
     if (early && !skip_zero && syndrome_is_zero(g, sc->s)) { it = 0; done = 1; }
     for (int32_t t = 1; !done && t <= L; ++t) {
         check_update(g, sc->s, sc->eta, sc->x, w, t);
         bit_update(g, r, sc->eta, sc->s);
-        if (early && syndrome_is_zero(g, sc->s)) { it = t; done = 1; }
+        if (early && t % early == 0 && syndrome_is_zero(g, sc->s)) { it = t; done = 1; }
     }
     for (int32_t j = 0; j < g->n; ++j) {
         if (bits) bits[j] = (uint8_t)hard_bit(sc->s[j]);
@@ -323,14 +327,16 @@ static int run_batch(const tanner_t *g, const float *llr, int32_t B, int32_t L, 
 /* ------------------------------------------------------------------------ */
 /* Exported entry points.  All buffers are host memory, row-major:          */
 /*   H m x n (0/1), llr B x n, bits B x n, post B x n, iters B, ok B.       */
-/* Output pointers may be NULL.  Returns 0, -1 (bad argument / no memory)   */
-/* or -2 (H not 0/1, or a row of degree 1).                                  */
+/* Output pointers may be NULL.  early_exit: 0 runs all max_iter            */
+/* iterations; k >= 1 tests for a codeword before the first iteration and   */
+/* after every k-th one.  Returns 0, -1 (bad argument / no memory) or -2    */
+/* (H not 0/1, or a row of degree 1).                                        */
 /* ------------------------------------------------------------------------ */
 
 int oracle_minsum_decode(const uint8_t *H, int32_t m, int32_t n, const float *llr, int32_t B,
                          int32_t max_iter, int32_t early_exit, uint8_t *bits, float *post,
                          int32_t *iters, uint8_t *ok, int32_t nthreads) {
-    if (!H || m < 1 || n < 1 || B < 0 || max_iter < 0 || (B > 0 && !llr)) return -1;
+    if (!H || m < 1 || n < 1 || B < 0 || max_iter < 0 || early_exit < 0 || (B > 0 && !llr)) return -1;
     tanner_t g;
     int st = tanner_build(H, m, n, &g);
     if (st) return st;
@@ -348,8 +354,8 @@ int oracle_nms_decode(const uint8_t *H, int32_t m, int32_t n, const float *llr, 
                       int32_t max_iter, int32_t early_exit, const float *alpha, const float *beta,
                       int32_t T, int32_t n_classes, uint8_t *bits, float *post, int32_t *iters,
                       uint8_t *ok, int32_t nthreads) {
-    if (!H || m < 1 || n < 1 || B < 0 || max_iter < 0 || max_iter > T || !alpha || !beta ||
-        (B > 0 && !llr))
+    if (!H || m < 1 || n < 1 || B < 0 || max_iter < 0 || max_iter > T || early_exit < 0 || !alpha ||
+        !beta || (B > 0 && !llr))
         return -1;
     tanner_t g;
     int st = tanner_build(H, m, n, &g);

@@ -25,6 +25,7 @@ int decode(const ldpc_graph *g, const float *llr, int32_t B, int32_t L, uint32_t
     int st = check_common(g, llr, B, L, bits, iters);
     if (st) return st;
     if ((flags & LDPC_FORCE_STREAM) && (flags & LDPC_FORCE_ONCHIP)) return LDPC_EINVAL;
+    if (flags & ~ldpc::kKnownFlags) return LDPC_EINVAL;
     if (B == 0) return LDPC_OK;
     if (use_onchip(*g, flags)) {
         if (!ldpc::onchip_fits(*g)) return LDPC_EUNSUPPORTED;
@@ -61,7 +62,7 @@ extern "C" size_t ldpc_multi_workspace_bytes(int32_t njobs) { return ldpc::onchi
 
 extern "C" int ldpc_minsum_decode_multi(const ldpc_job *jobs, int32_t njobs, int32_t max_iter, uint32_t flags,
                                         void *ws_dev, size_t ws_bytes, hipStream_t stream) {
-    if (!jobs || njobs < 1 || max_iter < 0) return LDPC_EINVAL;
+    if (!jobs || njobs < 1 || max_iter < 0 || (flags & ~ldpc::kKnownFlags)) return LDPC_EINVAL;
     int device = -1;
     for (int32_t k = 0; k < njobs; ++k) {
         const ldpc_job &j = jobs[k];

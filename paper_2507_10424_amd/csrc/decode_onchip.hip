@@ -212,12 +212,13 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
         sh->red[0] = sh->red[1] = 0u;
     }
     __syncthreads();
-    int32_t fr[kF], tt[kF], gen[kF];
+    int32_t fr[kF], tt[kF], gen[kF], ph[kF]; // ph = (tt - 1) mod the test period
 #pragma unroll
     for (int q = 0; q < kF; ++q) {
         fr[q] = __builtin_amdgcn_readfirstlane(sh->first[q]); // uniform: kept in scalar registers
         tt[q] = 1;
         gen[q] = 0;
+        ph[q] = 0;
     }
     vf2 eprev[RPT][DC];
     vf2 rc[CPT];
@@ -245,6 +246,7 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
             fr[q] = __builtin_amdgcn_readfirstlane(fr[q]);
             tt[q] = __builtin_amdgcn_readfirstlane(tt[q]);
             gen[q] = __builtin_amdgcn_readfirstlane(gen[q]);
+            ph[q] = __builtin_amdgcn_readfirstlane(ph[q]);
         }
         bool live = false;
 #pragma unroll
@@ -326,8 +328,10 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
 #pragma unroll
         for (int q = 0; q < kF; ++q) {
             if (fr[q] >= B) continue;
-            const bool clean = ((U >> q) & 1u) == 0u;
-            if (!((early && clean) || tt[q] > L)) continue;
+            // a codeword test is due when the decision's iteration tt - 1 is
+            // a multiple of the period (early = 0: never)
+            const bool clean = ((U >> q) & 1u) == 0u && ph[q] == 0 && early != 0;
+            if (!(clean || tt[q] > L)) continue;
             fin |= 1u << q;
             const int32_t f = fr[q];
 #pragma unroll
@@ -340,8 +344,8 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
                 }
             }
             if (tid == 0) {
-                iters[f] = (early && clean) ? tt[q] - 1 : L;
-                if (ok) ok[f] = clean ? 1 : 0;
+                iters[f] = clean ? tt[q] - 1 : L;
+                if (ok) ok[f] = ((U >> q) & 1u) == 0u ? 1 : 0;
             }
             const int32_t nf = __builtin_amdgcn_readfirstlane(sh->next[q][gen[q] & 1]);
             if (tid == 0) sh->next[q][(gen[q] + 1) & 1] = (int32_t)atomicAdd(queue, 1u);
@@ -385,7 +389,11 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
             }
         }
 #pragma unroll
-        for (int q = 0; q < kF; ++q) tt[q] = ((fin >> q) & 1u) ? 1 : tt[q] + 1;
+        for (int q = 0; q < kF; ++q) {
+            const bool refilled = (fin >> q) & 1u;
+            tt[q] = refilled ? 1 : tt[q] + 1;
+            ph[q] = (refilled || ph[q] + 1 == early) ? 0 : ph[q] + 1;
+        }
         __syncthreads();
     }
 }
@@ -565,7 +573,7 @@ int onchip_decode(const ldpc_graph &g, const float *llr, int32_t B, int32_t L, u
     int st = launch_grid((const void *)fn, threads, lds, g.num_cu, B, g.tuning.set ? g.tuning.wg_per_cu : 0, &grid);
     if (st) return st;
     uint32_t *queue = (uint32_t *)ws;
-    const int32_t early = (flags & LDPC_NO_EARLY_EXIT) ? 0 : 1;
+    const int32_t early = test_period(flags);
     const Job J = make_job(g, v, llr, B, bits, post, iters, ok, alpha, beta, queue);
     k_zero_words<<<1, 64, 0, stream>>>(queue, 1);
     timed_launch(K_ONCHIP, stream, [&] { fn<<<grid, threads, lds, stream>>>(J, L, early); });
@@ -617,7 +625,7 @@ int onchip_decode_multi(const ldpc_job *jobs, int32_t njobs, int32_t L, uint32_t
         jt.job[nj++] = J;
     }
     jt.njobs = nj;
-    const int32_t early = (flags & LDPC_NO_EARLY_EXIT) ? 0 : 1;
+    const int32_t early = test_period(flags);
     if (frames == 0 && wide.empty()) return LDPC_OK;
     k_zero_words<<<1, 64, 0, stream>>>(queues, njobs);
     if (frames > 0) {

@@ -237,7 +237,7 @@ __global__ __launch_bounds__(512) void k_bit(const int32_t *__restrict__ col_ptr
                                              float *__restrict__ s, const float *__restrict__ eta,
                                              uint32_t *__restrict__ done, const uint32_t *__restrict__ unsat_cur,
                                              uint32_t *__restrict__ unsat_next, int32_t *__restrict__ conv, int32_t t,
-                                             int32_t early) {
+                                             int32_t test_now) {
     const uint32_t bid = xcd_swizzle(blockIdx.x, gridDim.x);
     const int32_t tile = bid / col_blocks;
     const int32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -247,7 +247,7 @@ __global__ __launch_bounds__(512) void k_bit(const int32_t *__restrict__ col_ptr
     const int32_t f = tile * kTile + lane;
     bool act = !done[f];
     if (col >= n || !__any(act)) return;
-    const bool stop = act && early && unsat_cur[f] == 0u;
+    const bool stop = act && test_now && unsat_cur[f] == 0u;
     if (cb == 0 && w == 0) { // the wavefront of column 0 keeps the per-frame flags
         if (stop) {
             done[f] = 1u;
@@ -342,7 +342,7 @@ int stream_decode(const ldpc_graph &g, const float *llr, int32_t B, int32_t L, u
     if (ws == nullptr || ws_bytes < need) return LDPC_EWORKSPACE;
     const int32_t nt = (int32_t)tiles_of(B);
     const int32_t frames = nt * kTile;
-    const int32_t early = (flags & LDPC_NO_EARLY_EXIT) ? 0 : 1;
+    const int32_t period = test_period(flags); // 0: no early exit
     // wavefronts per workgroup of the check / bit kernels (tuning record, else 4)
     const int32_t waves = (g.tuning.set && g.tuning.stream_waves > 0) ? g.tuning.stream_waves : 4;
     const int32_t row_blocks = (g.m + waves - 1) / waves;
@@ -372,7 +372,8 @@ int stream_decode(const ldpc_graph &g, const float *llr, int32_t B, int32_t L, u
         timed_launch(K_BIT, stream, [&] {
             k_bit<<<nt * col_blocks, 64 * waves, 0, stream>>>(g.col_ptr, g.csc_edge, g.n, g.E, col_blocks, w.r, w.s, w.eta,
                                                        w.done, w.unsat[t & 1], w.unsat[(t + 1) & 1], w.conv, t,
-                                                       early);
+                                                       // is the decision of iteration t - 1 tested?
+                                                       (period > 0 && (t - 1) % period == 0) ? 1 : 0);
         });
     }
     uint32_t *unsat_final = w.unsat[(L + 1) & 1];

@@ -95,6 +95,16 @@ template <class F> inline void timed_launch(int kid, hipStream_t s, F &&fn) {
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// Flag bits the decode entry points accept.
+constexpr uint32_t kKnownFlags = LDPC_NO_EARLY_EXIT | LDPC_FORCE_STREAM | LDPC_FORCE_ONCHIP | LDPC_CHECK_PERIOD(0xff);
+
+// Codeword-test period of a decode: 0 = never (no early exit), else k >= 1.
+inline int32_t test_period(uint32_t flags) {
+    if (flags & LDPC_NO_EARLY_EXIT) return 0;
+    const int32_t k = (int32_t)((flags >> LDPC_CHECK_PERIOD_SHIFT) & 0xffu);
+    return k < 1 ? 1 : k;
+}
+
 // Linear workgroup id -> logical id such that consecutive logical ids stay on
 // one XCD.  Workgroups are dealt to the 8 XCDs round-robin, so XCD x runs the
 // ids x, x+8, x+16, ...; mapping them to a contiguous logical range keeps the

@@ -21,6 +21,16 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libldpc.so"
 LDPC_NO_EARLY_EXIT = 1 << 0
 LDPC_FORCE_STREAM = 1 << 1
 LDPC_FORCE_ONCHIP = 1 << 2
+LDPC_CHECK_PERIOD_SHIFT = 8
+
+
+def check_period(k: int) -> int:
+    """Flag bits for the codeword-test period k (1..255): with early exit a
+    frame is tested before the first iteration and after every k-th one."""
+    k = int(k)
+    if not 1 <= k <= 255:
+        raise ValueError("check period must be in 1..255")
+    return k << LDPC_CHECK_PERIOD_SHIFT
 
 _STATUS = {0: "LDPC_OK", -1: "LDPC_EINVAL", -2: "LDPC_EBADH", -3: "LDPC_ENOMEM", -4: "LDPC_EHIP",
            -5: "LDPC_EWORKSPACE", -6: "LDPC_EUNSUPPORTED"}

@@ -92,6 +92,8 @@ def main(argv=None):
     ap.add_argument("--min-errors", type=int, default=100)
     ap.add_argument("--seed", type=int, default=1234)
     ap.add_argument("--out", default=None, help="save alpha, beta and Adam state (.npz)")
+    ap.add_argument("--save-weights", default=None,
+                    help="save alpha, beta and the training record as JSON (the file bench.py reads)")
     ap.add_argument("--resume", default=None, help="continue from a saved .npz")
     args = ap.parse_args(argv)
 
@@ -130,6 +132,15 @@ def main(argv=None):
             "loss_first": float(hist[: min(10, hist.size)].mean()), "loss_last": float(hist[-10:].mean()),
             "alpha": tr.alpha.cpu().numpy().ravel().round(4).tolist(),
             "beta": tr.beta.cpu().numpy().ravel().round(4).tolist(), "eval": res}
+    if args.save_weights:
+        rec = {"code": args.code, "T": args.T, "alpha": tr.alpha.cpu().numpy().tolist(),
+               "beta": tr.beta.cpu().numpy().tolist(), "check_degrees": list(g.check_degrees),
+               "train": {k: line[k] for k in ("train_steps", "train_batch", "loss_first", "loss_last")}
+               | {"ebn0_range": [args.ebn0_lo, args.ebn0_hi], "lr": args.lr, "ckpt_every": args.ckpt_every,
+                  "seed": args.seed},
+               "eval": res}
+        with open(args.save_weights, "w") as f:
+            json.dump(rec, f, indent=1)
     print(json.dumps(line), flush=True)
 
 

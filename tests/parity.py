@@ -34,9 +34,10 @@ def gpu_decode(H, llr, L, flags=0, alpha=None, beta=None, graph=None, want_post=
 
 def oracle_decode(H, llr, L, flags=0, alpha=None, beta=None):
     early = not (flags & 1)
+    period = max(1, (flags >> 8) & 0xFF)  # codeword-test period in bits 8..15 of the flags
     if alpha is None:
-        return oracle.minsum_decode(H, llr, L, early_exit=early)
-    return oracle.nms_decode(H, llr, L, alpha, beta, early_exit=early)
+        return oracle.minsum_decode(H, llr, L, early_exit=early, check_period=period)
+    return oracle.nms_decode(H, llr, L, alpha, beta, early_exit=early, check_period=period)
 
 
 def assert_parity(gpu, ref, what=""):

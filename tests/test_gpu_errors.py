@@ -63,6 +63,9 @@ def test_decode_argument_errors(torch_dev):
                                   st) == -5
     assert lib.ldpc_minsum_decode(g.handle, P(llr), 10, 5, 0, P(bits), None, P(iters), None, None, 0, st) == -5
     assert lib.ldpc_minsum_decode(g.handle, None, 0, 5, 0, None, None, None, None, None, 0, st) == 0
+    for bad_flags in (1 << 3, 1 << 16, 6):  # unknown bits; both paths forced
+        assert lib.ldpc_minsum_decode(g.handle, P(llr), 10, 5, bad_flags, P(bits), None, P(iters), None, P(ws),
+                                      need, st) == -1
     a = torch.ones((4, len(g.check_degrees)), device=dev)
     assert lib.ldpc_nms_decode(g.handle, P(llr), 10, 5, 0, P(a), P(a), 4, P(bits), None, P(iters), None, P(ws),
                                need, st) == -1  # max_iter > T

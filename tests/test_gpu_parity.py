@@ -47,6 +47,21 @@ def test_iteration_limits(path, L, flags):
 
 
 @pytest.mark.parametrize("path", sorted(PATHS))
+@pytest.mark.parametrize("period", [2, 6])
+@pytest.mark.parametrize("L", [20, 23])
+def test_check_period(path, period, L):
+    """The paper's termination variant: codeword test before the first
+    iteration and after every k-th one (k = 6 in its GPU experiments)."""
+    H = wl.regular_ldpc(96, 48, 3, 6, seed=1)
+    llr = wl.bpsk_awgn_llr(None, 1.5, 0.5, seed=31 + period, n=96, batch=700)
+    gpu, ref = check(H, llr, L, PATHS[path] | (period << 8), what=f"period {period} {path}")
+    assert np.all((ref[2] % period == 0) | (ref[2] == L))
+    Hi = wl.random_irregular_code(500, 230, seed=4, dv_choices=(2, 3, 4, 6), max_row_degree=16)
+    llr = np.random.default_rng(period).normal(1.2, 1.4, size=(300, 500)).astype(np.float32)
+    check(Hi, llr, L, PATHS[path] | (period << 8), what=f"period {period} irregular {path}")
+
+
+@pytest.mark.parametrize("path", sorted(PATHS))
 def test_paper_example_codewords(path):
     from oracle_pins import codebook
     H = wl.paper_tanner_example()

@@ -50,3 +50,35 @@ def test_pins_catch_planted_mistake(mutant, tmp_path):
         except (AssertionError, ValueError):
             failed.append(pin.__name__)
     assert failed, f"no pin catches mutant {mutant}"
+
+
+@pytest.mark.parametrize("period", [1, 2, 6])
+def test_check_period_equals_stopped_fixed_length_runs(orc, period):
+    """The paper's termination variant (codeword test after every k-th
+    iteration, Sec. IV): decoding with period k must equal the fixed-length
+    decode (no early exit) stopped at the first multiple of k -- 0 included --
+    whose decision is a codeword, and the full-length decode when there is
+    none."""
+    H = wl.regular_ldpc(96, 48, 3, 6, seed=1)
+    rng = np.random.default_rng(90 + period)
+    llr = (2.0 / 0.63) * (1.0 + rng.normal(0.0, 0.8, size=(60, 96))).astype(np.float32)
+    L = 20
+    got = orc.minsum_decode(H, llr, L, check_period=period)
+    runs = {}
+    for f in range(llr.shape[0]):
+        stop = None
+        for t in range(0, L + 1, period):
+            if t not in runs:
+                runs[t] = orc.minsum_decode(H, llr, t, early_exit=False)
+            if runs[t][3][f]:
+                stop = t
+                break
+        ref = runs[stop] if stop is not None else orc.minsum_decode(H, llr[f:f + 1], L, early_exit=False)
+        fi = f if stop is not None else 0
+        assert np.array_equal(got[0][f], ref[0][fi])
+        assert np.array_equal(got[1][f].view(np.uint32), ref[1][fi].view(np.uint32))
+        assert got[2][f] == (stop if stop is not None else L)
+        assert got[3][f] == (1 if stop is not None else ref[3][fi])
+    if period > 1:  # the variant is not the per-iteration test in disguise
+        one = orc.minsum_decode(H, llr, L, check_period=1)
+        assert not np.array_equal(one[2], got[2])
