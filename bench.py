@@ -79,6 +79,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-nms", action="store_true", help="skip the learned-decoder comparison")
+    ap.add_argument("--no-dense", action="store_true", help="skip the dense (Algorithm 2) ablation")
     ap.add_argument("--profile-only", action="store_true", help="warmup + timed steps, no extras (for rocprofv3)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 256 MiB three times (calibrates the HBM byte counters of a profiler)")
@@ -91,7 +92,8 @@ def workload(name):
         H = wl.regular_ldpc(1024, 512, 3, 6, seed=2)
         return dict(name="(3,6)-regular n=1024 m=512, 65536 random codewords x 7 Eb/N0 points 1.0..4.0 dB, "
                          "L=50, early exit", H=H, batch=65536, ebn0=[1.0, 1.5, 2.0, 2.5, 3.0, 3.5, 4.0],
-                    L=50, rate=0.5, random_cw=True, seed_cw=200, seed_noise=300, nms_points=[1, 2, 3])
+                    L=50, rate=0.5, random_cw=True, seed_cw=200, seed_noise=300, nms_points=[1, 2, 3],
+                    dense_frames=1024)
     if name == "qc64800":
         H = wl.large_qc_code(seed=5)
         return dict(name="irregular QC n=64800 m=32400 Z=360, 4096 all-zero frames x Eb/N0 1.0..1.6 dB, L=50, "
@@ -274,7 +276,15 @@ def main():
             mism += int(np.any(gb != ob, axis=1).sum()) + int((gi != oi).sum())
         cpu["gpu_mismatches_on_sample"] = mism
 
-    nms = None if args.no_nms else nms_vs_plain(args, W, g, llrs, cws, flags, ws)
+    nms = dense = None
+    try:
+        if not args.no_nms:
+            nms = nms_vs_plain(args, W, g, llrs, cws, flags, ws)
+        if W.get("dense_frames") and not args.no_dense:
+            dense = dense_ablation(args, W, g, llrs, flags)
+    except ldpc.LdpcError as e:  # report, keep the main result
+        log(f"[bench] side measurement failed: {e}")
+        nms = nms if nms is not None else {"error": str(e)}
 
     line = {
         "metric": "coded Gbit/s & edge-msg/s (% HBM BW); neural vs plain Min-Sum at equal FER",
@@ -286,7 +296,7 @@ def main():
                    "tuning": tuning},
         "edge_msg_per_s": edge_msgs, "info_gbit_s": round(gbits * k_info / n, 3) if k_info else None,
         "mean_iters": round(tot_iters / frames_step, 3), "per_point": per_point,
-        "roofline": roofline, "cpu_baseline": cpu, "nms_vs_plain": nms,
+        "roofline": roofline, "cpu_baseline": cpu, "nms_vs_plain": nms, "dense_ablation": dense,
     }
     print(json.dumps(line), flush=True)
 
@@ -345,6 +355,41 @@ def nms_vs_plain(args, W, g, llrs, cws, flags, ws):
         row["speedup"] = round(row["learned"]["coded_gbit_s"] / row["plain"]["coded_gbit_s"], 3)
         res.append(row)
     return {"weights": os.path.relpath(path, ROOT), "T": T, "train": rec.get("train"), "points": res}
+
+
+def dense_ablation(args, W, g, llrs, flags):
+    """The paper's dense map-reduce form (Algorithm 2 on m x n matrices) against
+    the sparse decoder on the same frames: the first `dense_frames` frames of
+    the 2 dB batch.  Both outputs must agree."""
+    import torch
+    from paper_2507_10424_amd import ldpc
+    p = W["ebn0"].index(2.0)
+    x = llrs[p][: W["dense_frames"]].contiguous()
+    B, n = x.shape
+    L = W["L"]
+    dflags = flags & ~(ldpc.LDPC_FORCE_STREAM | ldpc.LDPC_FORCE_ONCHIP)
+    dws = torch.empty(max(1, ldpc.dense_workspace_bytes(g, B)), dtype=torch.uint8, device=x.device)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    res = {"frames": B, "ebn0_db": 2.0}
+    outs = {}
+    for name, fn in (("dense", lambda: ldpc.minsum_decode_dense(g, x, L, flags=dflags, workspace=dws)),
+                     ("sparse", lambda: ldpc.minsum_decode(g, x, L, flags=flags))):
+        fn()
+        torch.cuda.synchronize()
+        ev0.record()
+        outs[name] = fn()
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1)
+        res[name] = {"ms": round(ms, 4), "coded_gbit_s": round(B * n / (ms * 1e-3) / 1e9, 4)}
+    its = outs["dense"][2].to(torch.float64)
+    # dense message traffic: 12 m n bytes per frame-iteration (4 m n in iteration 1, which reads no eta)
+    mn = float(g.m) * float(g.n)
+    dbytes = float(((its >= 1).double() * 8 * mn + (its - 1).clamp(min=0) * 12 * mn).sum())
+    res["dense"]["message_gb_s"] = round(dbytes / (res["dense"]["ms"] * 1e-3) / 1e9, 1)
+    res["outputs_agree"] = bool(all(torch.equal(a, b) for a, b in zip(outs["dense"], outs["sparse"])))
+    res["sparse_over_dense"] = round(res["dense"]["ms"] / res["sparse"]["ms"], 1)
+    return res
 
 
 def bench_multi(args, W, dev, lib):

@@ -137,6 +137,23 @@ int ldpc_minsum_decode(const ldpc_graph *g, const float *llr_dev, int32_t B, int
                        uint8_t *ok_dev, void *ws_dev, size_t ws_bytes, hipStream_t stream);
 
 /*
+ * The paper's dense map-reduce form of the same decoder (Algorithm 2, Sec. III),
+ * as an ablation of the sparse design: per frame, lambda and eta are full
+ * m x n matrices (zero where H(i,j) = 0), each row reduction runs over all n
+ * columns and each column sum over all m rows, on HBM-resident frames-in-lanes
+ * tiles (12 m n message bytes per frame and iteration instead of 12 E).
+ * Arguments, outputs and errors are those of ldpc_minsum_decode; the outputs
+ * equal it except that a zero posterior may have the other sign.  Accepted
+ * flags: LDPC_NO_EARLY_EXIT and a check period.  Needs the graph's copy of the
+ * dense H, which ldpc_build_graph keeps when m * n <= 2^26; otherwise
+ * LDPC_EUNSUPPORTED.  ldpc_dense_workspace_bytes returns 0 in that case.
+ */
+size_t ldpc_dense_workspace_bytes(const ldpc_graph *g, int32_t B);
+int ldpc_minsum_decode_dense(const ldpc_graph *g, const float *llr_dev, int32_t B, int32_t max_iter,
+                             uint32_t flags, uint8_t *bits_dev, float *post_dev, int32_t *iters_dev,
+                             uint8_t *ok_dev, void *ws_dev, size_t ws_bytes, hipStream_t stream);
+
+/*
  * One job of a multi-code decode: a graph with its B frames and outputs,
  * laid out as for ldpc_minsum_decode (post_dev and ok_dev may be NULL).
  */
@@ -310,6 +327,8 @@ int ldpc_autotune(ldpc_graph *g, int32_t B, int32_t max_iter, float ebn0_db, voi
  *   kernel 0  streaming check-node kernel
  *   kernel 1  streaming bit-node kernel
  *   kernel 2  on-chip whole-decode kernel
+ *   kernel 3  dense row-reduction kernel
+ *   kernel 4  dense column-sum kernel
  * Errors: LDPC_EINVAL (unknown kernel), LDPC_EHIP.
  */
 int ldpc_timing_enable(int on);

@@ -58,6 +58,23 @@ extern "C" int ldpc_nms_decode(const ldpc_graph *g, const float *llr_dev, int32_
                   ws_dev, ws_bytes, stream);
 }
 
+extern "C" size_t ldpc_dense_workspace_bytes(const ldpc_graph *g, int32_t B) {
+    if (!g || B <= 0 || g->dense_h == nullptr) return 0;
+    return ldpc::dense_workspace_bytes(*g, B);
+}
+
+extern "C" int ldpc_minsum_decode_dense(const ldpc_graph *g, const float *llr_dev, int32_t B, int32_t max_iter,
+                                        uint32_t flags, uint8_t *bits_dev, float *post_dev, int32_t *iters_dev,
+                                        uint8_t *ok_dev, void *ws_dev, size_t ws_bytes, hipStream_t stream) {
+    int st = check_common(g, llr_dev, B, max_iter, bits_dev, iters_dev);
+    if (st) return st;
+    const uint32_t allowed = LDPC_NO_EARLY_EXIT | LDPC_CHECK_PERIOD(0xff);
+    if (flags & ~allowed) return LDPC_EINVAL;
+    if (B == 0) return LDPC_OK;
+    return ldpc::dense_decode(*g, llr_dev, B, max_iter, flags, bits_dev, post_dev, iters_dev, ok_dev, ws_dev,
+                              ws_bytes, stream);
+}
+
 extern "C" size_t ldpc_multi_workspace_bytes(int32_t njobs) { return ldpc::onchip_multi_workspace_bytes(njobs); }
 
 extern "C" int ldpc_minsum_decode_multi(const ldpc_job *jobs, int32_t njobs, int32_t max_iter, uint32_t flags,

@@ -385,3 +385,211 @@ int stream_decode(const ldpc_graph &g, const float *llr, int32_t B, int32_t L, u
 }
 
 } // namespace ldpc
+
+// ---------------------------------------------------------------------------
+// Dense map-reduce decoder (Algorithm 2, Sec. III), kept as an ablation of the
+// sparse design.  Same frames-in-lanes tiles, but lambda and eta are full
+// m x n matrices per frame: eta[tile][i][j][64], zero wherever H(i,j) = 0.
+// Per iteration and frame it moves 12 m n bytes of messages (read + write in
+// the row reductions, read in the column sums) instead of 12 E.
+//   row kernel     per (row i, frame): lambda(i,j) = s(j) H(i,j) - eta(i,j)
+//                  (s = r and eta = 0 in iteration 1) for every j; min0, its
+//                  first position, min1 and the sign parity over the j with
+//                  H(i,j) = 1; the syndrome of the previous decision; then
+//                  eta(i,j) = H(i,j) sign(lambda(i,j)) (total sign) (the other
+//                  bits' minimum) for every j (eq. etaCalculation, with the
+//                  argmin entry taking min1 as Observation 1 says).
+//   column kernel  per (bit j, frame): s(j) = (sum over all i ascending of
+//                  eta(i,j), from +0) + r(j) (eq. sCalculation).
+// The zero entries add only +-0 to the column sums, so the outputs equal the
+// sparse decoders' up to the sign of a zero posterior.
+// ---------------------------------------------------------------------------
+namespace ldpc {
+namespace {
+
+__global__ __launch_bounds__(512) void k_dense_row(const uint8_t *__restrict__ H, int32_t m, int32_t n,
+                                                   int32_t row_blocks, const float *__restrict__ r,
+                                                   const float *__restrict__ s, float *__restrict__ eta,
+                                                   const uint32_t *__restrict__ done, uint32_t *__restrict__ unsat,
+                                                   int32_t t) {
+    const uint32_t bid = xcd_swizzle(blockIdx.x, gridDim.x);
+    const int32_t tile = bid / row_blocks;
+    const int32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int32_t row = (bid % row_blocks) * (int32_t)(blockDim.x >> 6) + w;
+    const int lane = threadIdx.x & 63;
+    const int32_t f = tile * kTile + lane;
+    const bool act = !done[f];
+    if (row >= m || !__any(act)) return;
+    const float *sv = (t == 1 ? r : s) + (size_t)tile * n * kTile + lane;
+    float *et = eta + ((size_t)tile * m + row) * (size_t)n * kTile + lane;
+    const uint8_t *h = H + (size_t)row * n;
+    float min0 = __builtin_inff(), min1 = __builtin_inff();
+    int32_t am = -1;
+    uint32_t par = 0, syn = 0;
+    for (int32_t j = 0; j < n; ++j) {
+        const bool hj = h[j] != 0;
+        const float sj = sv[(size_t)j * kTile];
+        const float lam = sj * (hj ? 1.0f : 0.0f) - (t == 1 ? 0.0f : et[(size_t)j * kTile]);
+        if (hj) {
+            syn ^= sj < 0.0f;
+            par ^= lam < 0.0f;
+            const float a = fabsf(lam);
+            if (a < min0) {
+                min1 = min0;
+                min0 = a;
+                am = j;
+            } else if (a < min1) {
+                min1 = a;
+            }
+        }
+    }
+    if (act) {
+        for (int32_t j = 0; j < n; ++j) {
+            const bool hj = h[j] != 0;
+            float v = 0.0f;
+            if (hj) {
+                const float sj = sv[(size_t)j * kTile];
+                const float lam = sj - (t == 1 ? 0.0f : et[(size_t)j * kTile]);
+                const float mag = (j == am) ? min1 : min0;
+                v = (par ^ (lam < 0.0f ? 1u : 0u)) ? -mag : mag;
+            }
+            et[(size_t)j * kTile] = v;
+        }
+        if (syn) unsat[f] = 1u;
+    }
+}
+
+__global__ __launch_bounds__(512) void k_dense_col(int32_t m, int32_t n, int32_t col_blocks,
+                                                   const float *__restrict__ r, float *__restrict__ s,
+                                                   const float *__restrict__ eta, uint32_t *__restrict__ done,
+                                                   const uint32_t *__restrict__ unsat_cur,
+                                                   uint32_t *__restrict__ unsat_next, int32_t *__restrict__ conv,
+                                                   int32_t t, int32_t test_now) {
+    const uint32_t bid = xcd_swizzle(blockIdx.x, gridDim.x);
+    const int32_t tile = bid / col_blocks;
+    const int32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int32_t cb = bid % col_blocks;
+    const int32_t col = cb * (int32_t)(blockDim.x >> 6) + w;
+    const int lane = threadIdx.x & 63;
+    const int32_t f = tile * kTile + lane;
+    bool act = !done[f];
+    if (col >= n || !__any(act)) return;
+    const bool stop = act && test_now && unsat_cur[f] == 0u;
+    if (cb == 0 && w == 0) { // the wavefront of column 0 keeps the per-frame flags
+        if (stop) {
+            done[f] = 1u;
+            conv[f] = t - 1;
+        } else if (act) {
+            unsat_next[f] = 0u;
+        }
+    }
+    act = act && !stop;
+    if (!__any(act)) return;
+    const float *et = eta + (size_t)tile * m * (size_t)n * kTile + (size_t)col * kTile + lane;
+    float acc = 0.0f;
+    for (int32_t i = 0; i < m; ++i) acc = acc + et[(size_t)i * n * kTile];
+    const size_t o = ((size_t)tile * n + col) * kTile + lane;
+    if (act) s[o] = acc + r[o];
+}
+
+// Syndrome of the final decision, over the dense rows.
+__global__ __launch_bounds__(512) void k_dense_syndrome(const uint8_t *__restrict__ H, int32_t m, int32_t n,
+                                                        int32_t row_blocks, const float *__restrict__ sv_all,
+                                                        const uint32_t *__restrict__ done,
+                                                        uint32_t *__restrict__ unsat) {
+    const uint32_t bid = xcd_swizzle(blockIdx.x, gridDim.x);
+    const int32_t tile = bid / row_blocks;
+    const int32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int32_t row = (bid % row_blocks) * (int32_t)(blockDim.x >> 6) + w;
+    const int lane = threadIdx.x & 63;
+    const int32_t f = tile * kTile + lane;
+    const bool act = !done[f];
+    if (row >= m || !__any(act)) return;
+    const float *sv = sv_all + (size_t)tile * n * kTile + lane;
+    const uint8_t *h = H + (size_t)row * n;
+    uint32_t syn = 0;
+    for (int32_t j = 0; j < n; ++j)
+        if (h[j]) syn ^= sv[(size_t)j * kTile] < 0.0f;
+    if (act && syn) unsat[f] = 1u;
+}
+
+struct DenseWs {
+    float *r, *s, *eta;
+    uint32_t *done, *unsat[2];
+    int32_t *conv;
+};
+
+DenseWs carve_dense(const ldpc_graph &g, int32_t B, void *base, size_t *total) {
+    const size_t nt = tiles_of(B);
+    const size_t fr = nt * kTile;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off = align_up(off + bytes, 256);
+        return o;
+    };
+    const size_t o_r = take(nt * (size_t)g.n * kTile * 4);
+    const size_t o_s = take(nt * (size_t)g.n * kTile * 4);
+    const size_t o_e = take(nt * (size_t)g.m * (size_t)g.n * kTile * 4);
+    const size_t o_d = take(fr * 4);
+    const size_t o_u0 = take(fr * 4);
+    const size_t o_u1 = take(fr * 4);
+    const size_t o_c = take(fr * 4);
+    if (total) *total = off;
+    DenseWs w{};
+    char *b = (char *)base;
+    if (b) {
+        w.r = (float *)(b + o_r);
+        w.s = (float *)(b + o_s);
+        w.eta = (float *)(b + o_e);
+        w.done = (uint32_t *)(b + o_d);
+        w.unsat[0] = (uint32_t *)(b + o_u0);
+        w.unsat[1] = (uint32_t *)(b + o_u1);
+        w.conv = (int32_t *)(b + o_c);
+    }
+    return w;
+}
+
+} // namespace
+
+size_t dense_workspace_bytes(const ldpc_graph &g, int32_t B) {
+    size_t total = 0;
+    carve_dense(g, B, nullptr, &total);
+    return total;
+}
+
+int dense_decode(const ldpc_graph &g, const float *llr, int32_t B, int32_t L, uint32_t flags, uint8_t *bits,
+                 float *post, int32_t *iters, uint8_t *ok, void *ws, size_t ws_bytes, hipStream_t stream) {
+    if (g.dense_h == nullptr) return LDPC_EUNSUPPORTED;
+    size_t need = 0;
+    DenseWs w = carve_dense(g, B, ws, &need);
+    if (ws == nullptr || ws_bytes < need) return LDPC_EWORKSPACE;
+    const int32_t nt = (int32_t)tiles_of(B);
+    const int32_t frames = nt * kTile;
+    const int32_t period = test_period(flags);
+    const int32_t waves = 4;
+    const int32_t row_blocks = (g.m + waves - 1) / waves;
+    const int32_t col_blocks = (g.n + waves - 1) / waves;
+    const int32_t nchunks = (g.n + 63) / 64;
+    k_flags_init<<<(frames + 255) / 256, 256, 0, stream>>>(B, frames, w.done, w.unsat[0], w.unsat[1], w.conv);
+    k_to_tiles<<<nt * nchunks, 256, 0, stream>>>(llr, B, g.n, w.r);
+    for (int32_t t = 1; t <= L; ++t) {
+        timed_launch(K_DENSE_ROW, stream, [&] {
+            k_dense_row<<<nt * row_blocks, 64 * waves, 0, stream>>>(g.dense_h, g.m, g.n, row_blocks, w.r, w.s, w.eta,
+                                                                    w.done, w.unsat[t & 1], t);
+        });
+        timed_launch(K_DENSE_COL, stream, [&] {
+            k_dense_col<<<nt * col_blocks, 64 * waves, 0, stream>>>(
+                g.m, g.n, col_blocks, w.r, w.s, w.eta, w.done, w.unsat[t & 1], w.unsat[(t + 1) & 1], w.conv, t,
+                (period > 0 && (t - 1) % period == 0) ? 1 : 0);
+        });
+    }
+    uint32_t *unsat_final = w.unsat[(L + 1) & 1];
+    k_dense_syndrome<<<nt * row_blocks, 64 * waves, 0, stream>>>(g.dense_h, g.m, g.n, row_blocks,
+                                                                 L == 0 ? w.r : w.s, w.done, unsat_final);
+    k_finalize<<<(B + 255) / 256, 256, 0, stream>>>(B, L, w.conv, unsat_final, iters, ok);
+    k_from_tiles<<<nt * nchunks, 256, 0, stream>>>(w.r, w.s, w.conv, B, g.n, L, post, bits);
+    return hipGetLastError() == hipSuccess ? LDPC_OK : LDPC_EHIP;
+}
+
+} // namespace ldpc

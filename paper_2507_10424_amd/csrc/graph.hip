@@ -162,8 +162,10 @@ void free_graph_arrays(ldpc_graph *g) {
     (void)hipFree(g->row_class);
     (void)hipFree(g->edge_pos);
     (void)hipFree(g->edge_tab);
+    (void)hipFree(g->dense_h);
     g->row_ptr = g->col_idx = g->col_ptr = g->csc_edge = g->row_class = g->edge_pos = nullptr;
     g->edge_tab = nullptr;
+    g->dense_h = nullptr;
 }
 
 template <class T> hipError_t dalloc(T **p, size_t count) {
@@ -314,7 +316,14 @@ extern "C" int ldpc_build_graph(const uint8_t *H_dev, int32_t m, int32_t n, hipS
         delete g;
         return LDPC_EHIP;
     }
-    const int st = build(H_dev, m, n, stream, g);
+    int st = build(H_dev, m, n, stream, g);
+    if (st == LDPC_OK && (size_t)m * (size_t)n <= ldpc::kDenseMaxBytes) {
+        if (dalloc(&g->dense_h, (size_t)m * (size_t)n) != hipSuccess)
+            st = LDPC_ENOMEM;
+        else if (hipMemcpyAsync(g->dense_h, H_dev, (size_t)m * (size_t)n, hipMemcpyDeviceToDevice, stream) !=
+                 hipSuccess)
+            st = LDPC_EHIP;
+    }
     if (st != LDPC_OK) {
         (void)hipStreamSynchronize(stream);
         free_graph_arrays(g);

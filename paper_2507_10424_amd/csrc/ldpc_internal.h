@@ -30,6 +30,9 @@ struct ldpc_graph {
     // On-chip path tables (built when n and E are below 2^16): per CSR edge
     // the bit index in the low 16 bits and the CSC slot in the high 16 bits.
     uint32_t *edge_tab = nullptr; // E, or null
+    // Device copy of the dense m x n H (0/1 bytes) for the dense map-reduce
+    // decoder, kept when m * n <= kDenseMaxBytes; null otherwise.
+    uint8_t *dense_h = nullptr;
     // Launch choices picked by ldpc_autotune or set by ldpc_graph_set_tuning.
     struct {
         bool set = false;
@@ -70,8 +73,14 @@ size_t onchip_multi_workspace_bytes(int32_t njobs);
 int onchip_decode_multi(const ldpc_job *jobs, int32_t njobs, int32_t L, uint32_t flags, void *ws, size_t ws_bytes,
                         hipStream_t stream);
 
+// Dense map-reduce decoder (Algorithm 2 on m x n matrices): workspace, launch.
+constexpr size_t kDenseMaxBytes = size_t(1) << 26;
+size_t dense_workspace_bytes(const ldpc_graph &g, int32_t B);
+int dense_decode(const ldpc_graph &g, const float *llr, int32_t B, int32_t L, uint32_t flags, uint8_t *bits,
+                 float *post, int32_t *iters, uint8_t *ok, void *ws, size_t ws_bytes, hipStream_t stream);
+
 // Kernel ids of the optional per-kernel timing (ldpc_timing_read).
-enum KernelId { K_CHECK = 0, K_BIT = 1, K_ONCHIP = 2, K_COUNT = 3 };
+enum KernelId { K_CHECK = 0, K_BIT = 1, K_ONCHIP = 2, K_DENSE_ROW = 3, K_DENSE_COL = 4, K_COUNT = 5 };
 bool timing_on();
 void timing_record(int kid, hipEvent_t a, hipEvent_t b);
 

@@ -87,6 +87,11 @@ def load_library():
     lib.ldpc_decode_workspace_bytes.restype = ctypes.c_size_t
     lib.ldpc_minsum_decode.argtypes = [_vp, _vp, _i32, _i32, _u32, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
     lib.ldpc_minsum_decode.restype = ctypes.c_int
+    lib.ldpc_dense_workspace_bytes.argtypes = [_vp, _i32]
+    lib.ldpc_dense_workspace_bytes.restype = ctypes.c_size_t
+    lib.ldpc_minsum_decode_dense.argtypes = [_vp, _vp, _i32, _i32, _u32, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t,
+                                             _vp]
+    lib.ldpc_minsum_decode_dense.restype = ctypes.c_int
     lib.ldpc_status_string.argtypes = [ctypes.c_int]
     lib.ldpc_status_string.restype = ctypes.c_char_p
     lib.ldpc_nms_decode.argtypes = [_vp, _vp, _i32, _i32, _u32, _vp, _vp, _i32, _vp, _vp, _vp, _vp, _vp,
@@ -220,6 +225,29 @@ def minsum_decode(g: Graph, llr: torch.Tensor, max_iter: int, flags: int = 0, wa
                                     _stream(llr.device))
     if st:
         raise LdpcError(st, "ldpc_minsum_decode")
+    return bits, post, iters, ok
+
+
+def dense_workspace_bytes(g: Graph, B: int) -> int:
+    return int(load_library().ldpc_dense_workspace_bytes(g.handle, int(B)))
+
+
+def minsum_decode_dense(g: Graph, llr: torch.Tensor, max_iter: int, flags: int = 0, want_post: bool = True,
+                        workspace: torch.Tensor | None = None, out=None):
+    """ldpc_minsum_decode_dense: the dense map-reduce form (Algorithm 2), an
+    ablation of the sparse decoders.  Same outputs as minsum_decode."""
+    llr = _check_llr(g, llr)
+    B = llr.shape[0]
+    bits, post, iters, ok = out if out is not None else _outputs(B, g.n, llr.device, want_post)
+    if workspace is None:
+        workspace = torch.empty(max(dense_workspace_bytes(g, B), 1), dtype=torch.uint8, device=llr.device)
+    lib = load_library()
+    with torch.cuda.device(llr.device):
+        st = lib.ldpc_minsum_decode_dense(g.handle, _ptr(llr), B, int(max_iter), int(flags), _ptr(bits),
+                                          _ptr(post), _ptr(iters), _ptr(ok), _ptr(workspace), workspace.numel(),
+                                          _stream(llr.device))
+    if st:
+        raise LdpcError(st, "ldpc_minsum_decode_dense")
     return bits, post, iters, ok
 
 
