@@ -28,6 +28,33 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, AMD published
 VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # 32-bit VALU lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz
 
 
+# HBM bytes per launch of the dominant kernel, measured with rocprofv3
+# FETCH_SIZE and WRITE_SIZE (each in a run of its own, scaled by a plain copy:
+# FETCH x 2.000, WRITE x 1.000), averaged over the launches of one step.  Each
+# entry holds the hash of the kernel source it was taken with; once that file
+# changes the figure no longer applies and `traffic` is reported as null.
+# Summaries: profiles/hbm_bytes_qc64800_regular1024.md.
+MEASURED_TRAFFIC = {
+    ("regular1024", "onchip"): {"bytes": 608489285, "source": "decode_onchip.hip", "sha256_16": "e5ae54f2b205e750"},
+    ("qc64800", "check"): {"bytes": 10251460774, "source": "decode_stream.hip", "sha256_16": "05e9e4e489140852"},
+    ("qc64800", "bit"): {"bytes": 5691547662, "source": "decode_stream.hip", "sha256_16": "05e9e4e489140852"},
+}
+
+
+def measured_traffic(config: str, kernel: str):
+    import hashlib
+    rec = MEASURED_TRAFFIC.get((config, kernel))
+    if rec is None:
+        return None
+    path = os.path.join(ROOT, "paper_2507_10424_amd", "csrc", rec["source"])
+    try:
+        with open(path, "rb") as f:
+            cur = hashlib.sha256(f.read()).hexdigest()[:16]
+    except OSError:
+        return None
+    return rec["bytes"] if cur == rec["sha256_16"] else None
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -73,6 +100,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="regular1024", choices=["regular1024", "qc64800", "regular96", "multi8"])
     ap.add_argument("--no-autotune", action="store_true", help="skip the autotuner (library defaults)")
+    ap.add_argument("--tuning", default=None,
+                    help="set the tuning record instead of autotuning: path,variant,wg_per_cu,stream_waves,"
+                         "waves_per_simd (as printed by a tuned run)")
     ap.add_argument("--path", default="auto", choices=["auto", "stream", "onchip"])
     ap.add_argument("--check-period", type=int, default=1,
                     help="codeword test after every k-th iteration (the paper's GPU runs use 6)")
@@ -161,7 +191,12 @@ def main():
     log(f"[bench] inputs ready on the GPU in {time.time() - t0:.1f} s ({len(llrs)} x {B} x {n})")
 
     tuning = None
-    if not args.no_autotune and args.path == "auto":
+    if args.tuning:
+        p_, v_, w_, sw_, ws_ = (int(t) for t in args.tuning.split(","))
+        ldpc.set_tuning(g, p_, v_, w_, sw_, ws_)
+        tuning = ldpc.get_tuning(g)
+        log(f"[bench] tuning set: {tuning}")
+    elif not args.no_autotune and args.path == "auto":
         ta = time.time()
         tuning = ldpc.autotune(g, min(B, 16384), L, 2.0 if args.config != "qc64800" else 1.2)
         log(f"[bench] autotuned in {time.time() - ta:.1f} s: {tuning}")
@@ -233,7 +268,7 @@ def main():
         peak = VALU_PEAK_TOPS
         io = float(frames_step * (9 * n + 5))
         roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "Tops/s",
-                    "frac": round(achieved / peak, 4), "traffic": None, "kernel": dom,
+                    "frac": round(achieved / peak, 4), "traffic": measured_traffic(args.config, dom), "kernel": dom,
                     "lane_ops_per_frame_iter": ops_fi,
                     "kernel_ms_per_launch": round(dom_ms / dom_launches, 4), "launches_per_step": dom_launches,
                     "hbm_io_gb_s": round(io / (dom_ms * 1e-3) / 1e9, 1)}
@@ -243,8 +278,11 @@ def main():
         else:
             algo = float((its * (4 * E + 8 * n)).sum())
         achieved = algo / (dom_ms * 1e-3) / 1e9
+        traffic = measured_traffic(args.config, dom)
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                    "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                    "traffic_over_algorithmic": (round(traffic / (algo / dom_launches), 3) if traffic else None),
+                    "kernel": dom,
                     "kernel_ms_per_launch": round(dom_ms / dom_launches, 4), "launches_per_step": dom_launches}
 
     cpu = None

@@ -259,11 +259,24 @@ __global__ __launch_bounds__(512) void k_bit(const int32_t *__restrict__ col_ptr
     act = act && !stop;
     if (!__any(act)) return;
     const float *et = eta + (size_t)tile * E * kTile + lane;
-    float acc = 0.0f;
     const int32_t k0 = col_ptr[col], k1 = col_ptr[col + 1];
-    for (int32_t k = k0; k < k1; ++k) acc = acc + et[(size_t)csc_edge[k] * kTile];
     const size_t o = ((size_t)tile * n + col) * kTile + lane;
-    if (act) s[o] = acc + r[o];
+    const float rv = r[o];
+    float acc = 0.0f;
+    // Messages in groups of 8: every load of a group is issued before the
+    // first add, so a wavefront keeps up to 9 requests in flight instead of
+    // one; the adds still run in ascending check order.
+    for (int32_t k = k0; k < k1; k += 8) {
+        int32_t idx[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) idx[u] = csc_edge[k + u]; // in bounds: the table has 8 entries of padding
+        float ev[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) ev[u] = et[(size_t)(k + u < k1 ? idx[u] : idx[0]) * kTile];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc = (k + u < k1) ? acc + ev[u] : acc; // a select, not a branch
+    }
+    if (act) s[o] = acc + rv;
 }
 
 // Syndrome of the current decision only (after the last iteration).

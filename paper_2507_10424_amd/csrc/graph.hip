@@ -225,7 +225,8 @@ int build(const uint8_t *H, int32_t m, int32_t n, hipStream_t s, ldpc_graph *g) 
         for (int32_t i = 0; i < m; ++i) h_class[i] = h_row[i] ? rank[h_row[i]] : -1;
 
         if (dalloc(&g->row_ptr, m + 1) != hipSuccess || dalloc(&g->col_idx, E) != hipSuccess ||
-            dalloc(&g->col_ptr, n + 1) != hipSuccess || dalloc(&g->csc_edge, E) != hipSuccess ||
+            dalloc(&g->col_ptr, n + 1) != hipSuccess || dalloc(&g->csc_edge, E + 8) != hipSuccess || // 8 entries of padding: readers load groups of 8
+            hipMemsetAsync(g->csc_edge + E, 0, 8 * sizeof(int32_t), s) != hipSuccess ||
             dalloc(&g->row_class, m) != hipSuccess || dalloc(&g->edge_pos, E) != hipSuccess) {
             fail(LDPC_ENOMEM);
             break;

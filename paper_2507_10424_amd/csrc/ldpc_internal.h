@@ -24,7 +24,7 @@ struct ldpc_graph {
     int32_t *row_ptr = nullptr;   // m + 1
     int32_t *col_idx = nullptr;   // E: bit of each edge
     int32_t *col_ptr = nullptr;   // n + 1
-    int32_t *csc_edge = nullptr;  // E: CSR edge number of the k-th CSC entry
+    int32_t *csc_edge = nullptr;  // E (+ 8 padding entries): CSR edge number of the k-th CSC entry
     int32_t *row_class = nullptr; // m: degree class of the row (-1 for degree 0)
     int32_t *edge_pos = nullptr;  // E: CSC slot of each CSR edge (inverse of csc_edge)
     // On-chip path tables (built when n and E are below 2^16): per CSR edge
