@@ -470,6 +470,14 @@ def bench_multi(args, W, dev, lib):
 
     ms_each = timed(step_each)
     ms_multi = timed(step_multi)
+
+    # the same codes with 1/32 of the batches: here one shared persistent
+    # launch has to carry the small batches that underfill the GPU one by one
+    small_llrs = [x[: max(1, x.shape[0] // 32)].contiguous() for x in llrs]
+    small_jobs = list(zip(graphs, small_llrs))
+    small_bits = sum(x.shape[0] * x.shape[1] for x in small_llrs)
+    ms_small_multi = timed(lambda: ldpc.minsum_decode_multi(small_jobs, L, workspace=ws))
+    ms_small_each = timed(lambda: [ldpc.minsum_decode(g, x, L, workspace=ws) for g, x in small_jobs])
     gbits = bits / (ms_multi * 1e-3) / 1e9
     log(f"[bench] multi-code: one launch {ms_multi:.3f} ms/step ({gbits:.2f} Gbit/s), "
         f"one launch per code {ms_each:.3f} ms/step")
@@ -490,6 +498,10 @@ def bench_multi(args, W, dev, lib):
         "config": {"workload": W["name"], "frames": frames, "max_iter": L, "ebn0_db": W["ebn0"]},
         "edge_msg_per_s": 2.0 * edges_iters / (ms_multi * 1e-3), "mean_iters": round(iters / frames, 3),
         "ms_per_step_one_launch_per_code": round(ms_each, 4), "per_code": per_code,
+        "small_batches": {"frames": sum(x.shape[0] for x in small_llrs), "ms_one_call": round(ms_small_multi, 4),
+                          "ms_one_launch_per_code": round(ms_small_each, 4),
+                          "gbit_s_one_call": round(small_bits / (ms_small_multi * 1e-3) / 1e9, 3),
+                          "gbit_s_one_launch_per_code": round(small_bits / (ms_small_each * 1e-3) / 1e9, 3)},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
                      "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None, "kernel": "onchip_multi"},
         "cpu_baseline": None,

@@ -174,12 +174,15 @@ size_t ldpc_multi_workspace_bytes(int32_t njobs);
 
 /*
  * Min-Sum decoding of the frames of several codes (up to LDPC_MAX_JOBS
- * graphs, each with its own batch) in one persistent launch, with the
- * semantics of ldpc_minsum_decode for every frame (per-frame early exit; only
- * LDPC_NO_EARLY_EXIT is honoured among the flags).  Every graph must fit the
- * on-chip kernel and live on the current device.  Workgroups take frames
- * from per-job counters, largest job (frames x edges) first, and move to the
- * next job without waiting for the others.
+ * graphs, each with its own batch) in one call, with the semantics of
+ * ldpc_minsum_decode for every frame (per-frame early exit; LDPC_NO_EARLY_EXIT
+ * and the check period are honoured, the path flags are ignored).  Every graph
+ * must fit the on-chip kernel and live on the current device.  Jobs whose
+ * batch alone fills the GPU for several rounds of frames run as launches of
+ * their own kernels; the others share one persistent launch in which
+ * workgroups take frames from per-job counters, largest job (frames x edges)
+ * first, and move to the next job without waiting for the others.  All
+ * launches are enqueued on `stream` in this call.
  * Errors: LDPC_EINVAL (null or empty job list, null pointers in a job with
  * B > 0, B < 0, max_iter < 0), LDPC_EUNSUPPORTED (a graph does not fit, or
  * more than LDPC_MAX_JOBS jobs), LDPC_EWORKSPACE, LDPC_EHIP.

@@ -586,35 +586,63 @@ int onchip_decode_multi(const ldpc_job *jobs, int32_t njobs, int32_t L, uint32_t
                         hipStream_t stream) {
     if (njobs > kMaxJobs) return LDPC_EUNSUPPORTED;
     if (ws == nullptr || ws_bytes < onchip_multi_workspace_bytes(njobs)) return LDPC_EWORKSPACE;
-    // largest jobs first, so the last frames of the launch come from small jobs
+    // largest jobs first, so the last frames of the shared launch come from small jobs
     std::vector<int32_t> order(njobs);
     for (int32_t k = 0; k < njobs; ++k) order[k] = k;
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
         return (int64_t)jobs[a].B * jobs[a].g->E > (int64_t)jobs[b].B * jobs[b].g->E;
     });
+    // A job whose batch alone fills every CU for at least kOwnLaunchRounds
+    // rounds of frames gets a launch of its own kernel (its own LDS size,
+    // workgroup size and register budget); so does a job that only the
+    // widest variant fits.  The other jobs share one persistent launch, whose
+    // workgroup size and LDS are the maxima over them.
+    constexpr int64_t kOwnLaunchRounds = 4;
     JobTable jt{};
     int threads = 64;
     size_t lds = 0;
     int64_t frames = 0;
     int num_cu = 0;
     uint32_t *queues = (uint32_t *)ws;
-    std::vector<std::pair<Job, const ldpc_graph *>> wide; // jobs with a launch of their own
+    struct Own {
+        Job J;
+        KernelFn fn;
+        int threads;
+        size_t lds;
+        int num_cu;
+    };
+    std::vector<Own> own;
     int32_t nj = 0;
     for (int32_t k = 0; k < njobs; ++k) {
         const ldpc_job &jb = jobs[order[k]];
         const ldpc_graph &g = *jb.g;
         if (!onchip_fits(g)) return LDPC_EUNSUPPORTED;
-        int v = pick(g);
-        if (v == kWideVariant) // another variant that fits keeps the job in the shared launch
+        if (jb.B == 0) continue;
+        const int v_own = pick(g);
+        int v = v_own;
+        if (v == kWideVariant) // another variant that fits keeps the job eligible for the shared launch
             for (int c = 0; c < kNumVariants; ++c)
                 if (c != kWideVariant && variant_ok(g, c)) {
                     v = c;
                     break;
                 }
-        const Job J = make_job(g, v, jb.llr_dev, jb.B, jb.bits_dev, jb.post_dev, jb.iters_dev, jb.ok_dev, nullptr,
-                               nullptr, queues + k);
-        if (v == kWideVariant) {
-            if (jb.B > 0) wide.emplace_back(J, &g);
+        const KernelFn fn = kKernels[(g.tuning.set && g.tuning.waves_per_simd == 4) ? 1 : 0][v_own];
+        const int t_own = threads_for(g, kVariants[v_own]);
+        const size_t l_own = onchip_lds_bytes(g);
+        bool alone = v == kWideVariant;
+        if (!alone) {
+            int per_cu = 0;
+            if (hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l_own) !=
+                    hipSuccess ||
+                hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)fn, t_own, l_own) != hipSuccess)
+                return LDPC_EHIP;
+            const int64_t in_flight = (int64_t)(per_cu < 1 ? 1 : per_cu) * g.num_cu * kF;
+            alone = (int64_t)jb.B >= kOwnLaunchRounds * in_flight;
+        }
+        if (alone) {
+            own.push_back(Own{make_job(g, v_own, jb.llr_dev, jb.B, jb.bits_dev, jb.post_dev, jb.iters_dev, jb.ok_dev,
+                                       nullptr, nullptr, queues + k),
+                              fn, t_own, l_own, g.num_cu});
             continue;
         }
         const int t = threads_for(g, kVariants[v]);
@@ -622,28 +650,28 @@ int onchip_decode_multi(const ldpc_job *jobs, int32_t njobs, int32_t L, uint32_t
         lds = onchip_lds_bytes(g) > lds ? onchip_lds_bytes(g) : lds;
         frames += jb.B;
         num_cu = g.num_cu;
-        jt.job[nj++] = J;
+        jt.job[nj++] = make_job(g, v, jb.llr_dev, jb.B, jb.bits_dev, jb.post_dev, jb.iters_dev, jb.ok_dev, nullptr,
+                                nullptr, queues + k);
     }
     jt.njobs = nj;
     const int32_t early = test_period(flags);
-    if (frames == 0 && wide.empty()) return LDPC_OK;
+    if (frames == 0 && own.empty()) return LDPC_OK;
     k_zero_words<<<1, 64, 0, stream>>>(queues, njobs);
+    for (const Own &o : own) {
+        int grid = 0;
+        const int st = launch_grid((const void *)o.fn, o.threads, o.lds, o.num_cu, o.J.B, 0, &grid);
+        if (st) return st;
+        const Job J = o.J;
+        const KernelFn fn = o.fn;
+        const int t = o.threads;
+        const size_t l = o.lds;
+        timed_launch(K_ONCHIP, stream, [&] { fn<<<grid, t, l, stream>>>(J, L, early); });
+    }
     if (frames > 0) {
         int grid = 0;
         const int st = launch_grid((const void *)k_onchip_multi, threads, lds, num_cu, frames, 0, &grid);
         if (st) return st;
         timed_launch(K_ONCHIP, stream, [&] { k_onchip_multi<<<grid, threads, lds, stream>>>(jt, L, early); });
-    }
-    for (const auto &w : wide) {
-        const ldpc_graph &g = *w.second;
-        const KernelFn fn = kKernels[0][kWideVariant];
-        const int t = threads_for(g, kVariants[kWideVariant]);
-        const size_t l = onchip_lds_bytes(g);
-        int grid = 0;
-        const int st = launch_grid((const void *)fn, t, l, g.num_cu, w.first.B, 0, &grid);
-        if (st) return st;
-        const Job J = w.first;
-        timed_launch(K_ONCHIP, stream, [&] { fn<<<grid, t, l, stream>>>(J, L, early); });
     }
     return hipGetLastError() == hipSuccess ? LDPC_OK : LDPC_EHIP;
 }

@@ -30,7 +30,9 @@
 namespace ldpc {
 namespace {
 
-constexpr int kWaves = 4; // wavefronts per workgroup of the transpose kernels
+constexpr int kWaves = 4;       // wavefronts per workgroup of the transpose kernels
+constexpr int kRowsPerWave = 2; // rows per wavefront of the unrolled check kernel
+constexpr int kColsPerWave = 4; // bit columns per wavefront of the bit kernel
 
 struct StreamWs {
     float *r, *s, *eta;
@@ -168,10 +170,11 @@ __global__ __launch_bounds__(512) void k_check(const int32_t *__restrict__ row_p
     if (act && syn) unsat[f] = 1u;
 }
 
-// The same check update for graphs whose rows all have DC edges: the loop is
-// unrolled and every load of the row is issued before any use, so a
-// wavefront keeps 2 DC memory requests in flight.
-template <int DC>
+// The same check update for graphs whose rows all have DC edges, RPW rows
+// per wavefront: the loops are unrolled and every load of the wavefront's
+// rows is issued before any use, so it keeps 2 DC RPW requests in flight,
+// and there are RPW times fewer wavefronts to launch.
+template <int DC, int RPW>
 __global__ __launch_bounds__(512) void k_check_dc(const int32_t *__restrict__ col_idx,
                                                   const int32_t *__restrict__ row_class, int32_t m, int32_t n,
                                                   int64_t E, int32_t row_blocks, const float *__restrict__ r,
@@ -182,56 +185,72 @@ __global__ __launch_bounds__(512) void k_check_dc(const int32_t *__restrict__ co
     const uint32_t bid = xcd_swizzle(blockIdx.x, gridDim.x);
     const int32_t tile = bid / row_blocks;
     const int32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int32_t row = (bid % row_blocks) * (int32_t)(blockDim.x >> 6) + w;
+    const int32_t row0 = ((bid % row_blocks) * (int32_t)(blockDim.x >> 6) + w) * RPW;
     const int lane = threadIdx.x & 63;
     const int32_t f = tile * kTile + lane;
     const bool act = !done[f];
-    if (row >= m || !__any(act)) return;
+    if (row0 >= m || !__any(act)) return;
 
     const float *sv = (t == 1 ? r : s) + (size_t)tile * n * kTile + lane;
     float *et = eta + (size_t)tile * E * kTile + lane;
-    const int64_t e0 = (int64_t)row * DC; // rows of equal degree: CSR offsets are row * DC
-    float sj[DC], ev[DC];
+    float sj[RPW][DC], ev[RPW][DC];
 #pragma unroll
-    for (int k = 0; k < DC; ++k) sj[k] = sv[(size_t)col_idx[e0 + k] * kTile];
+    for (int q = 0; q < RPW; ++q) {
+        // rows of equal degree: CSR offsets are row * DC; a row past m repeats row0
+        const int64_t e0 = (int64_t)(row0 + q < m ? row0 + q : row0) * DC;
 #pragma unroll
-    for (int k = 0; k < DC; ++k) ev[k] = (t == 1) ? 0.0f : et[(size_t)(e0 + k) * kTile];
-    float x[DC];
-    float min0 = __builtin_inff(), min1 = __builtin_inff();
-    int32_t am = -1;
-    uint32_t par = 0, syn = 0;
+        for (int k = 0; k < DC; ++k) sj[q][k] = sv[(size_t)col_idx[e0 + k] * kTile];
 #pragma unroll
-    for (int k = 0; k < DC; ++k) {
-        syn ^= sj[k] < 0.0f;
-        x[k] = (t == 1) ? sj[k] : sj[k] - ev[k];
-        const float a = fabsf(x[k]);
-        par ^= x[k] < 0.0f;
-        if (a < min0) {
-            min1 = min0;
-            min0 = a;
-            am = k;
-        } else if (a < min1) {
-            min1 = a;
-        }
+        for (int k = 0; k < DC; ++k) ev[q][k] = (t == 1) ? 0.0f : et[(size_t)(e0 + k) * kTile];
     }
-    if (alpha != nullptr) {
-        const int32_t c = row_class[row];
-        const float al = alpha[(t - 1) * n_classes + c], be = beta[(t - 1) * n_classes + c];
-        const float v0 = fmaf(al, min0, -be), v1 = fmaf(al, min1, -be);
-        min0 = v0 > 0.0f ? v0 : 0.0f;
-        min1 = v1 > 0.0f ? v1 : 0.0f;
-    }
-    if (act) {
+    uint32_t syn = 0;
+#pragma unroll
+    for (int q = 0; q < RPW; ++q) {
+        const int32_t row = row0 + q;
+        if (row >= m) break;
+        float x[DC];
+        float min0 = __builtin_inff(), min1 = __builtin_inff();
+        int32_t am = -1;
+        uint32_t par = 0;
 #pragma unroll
         for (int k = 0; k < DC; ++k) {
-            const float mag = (k == am) ? min1 : min0;
-            et[(size_t)(e0 + k) * kTile] = (par ^ (x[k] < 0.0f ? 1u : 0u)) ? -mag : mag;
+            syn ^= sj[q][k] < 0.0f ? (1u << q) : 0u;
+            x[k] = (t == 1) ? sj[q][k] : sj[q][k] - ev[q][k];
+            const float a = fabsf(x[k]);
+            par ^= x[k] < 0.0f;
+            if (a < min0) {
+                min1 = min0;
+                min0 = a;
+                am = k;
+            } else if (a < min1) {
+                min1 = a;
+            }
         }
-        if (syn) unsat[f] = 1u;
+        if (alpha != nullptr) {
+            const int32_t c = row_class[row];
+            const float al = alpha[(t - 1) * n_classes + c], be = beta[(t - 1) * n_classes + c];
+            const float v0 = fmaf(al, min0, -be), v1 = fmaf(al, min1, -be);
+            min0 = v0 > 0.0f ? v0 : 0.0f;
+            min1 = v1 > 0.0f ? v1 : 0.0f;
+        }
+        if (act) {
+            const int64_t e0 = (int64_t)row * DC;
+#pragma unroll
+            for (int k = 0; k < DC; ++k) {
+                const float mag = (k == am) ? min1 : min0;
+                et[(size_t)(e0 + k) * kTile] = (par ^ (x[k] < 0.0f ? 1u : 0u)) ? -mag : mag;
+            }
+        }
     }
+    if (act && syn) unsat[f] = 1u; // some row of this wavefront is unsatisfied
 }
 
-// One wavefront = one bit column x one frame tile.
+// CPW bit columns x one frame tile per wavefront.  The first 8 messages of
+// every column are loaded (8 indices per column with one scalar load, then 8
+// message loads) before any add, so a wavefront keeps up to 9 CPW requests in
+// flight; longer columns continue in groups of 8.  The adds of a column run
+// in ascending check order from +0, then r is added.
+template <int CPW>
 __global__ __launch_bounds__(512) void k_bit(const int32_t *__restrict__ col_ptr, const int32_t *__restrict__ csc_edge,
                                              int32_t n, int64_t E, int32_t col_blocks, const float *__restrict__ r,
                                              float *__restrict__ s, const float *__restrict__ eta,
@@ -242,13 +261,13 @@ __global__ __launch_bounds__(512) void k_bit(const int32_t *__restrict__ col_ptr
     const int32_t tile = bid / col_blocks;
     const int32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int32_t cb = bid % col_blocks;
-    const int32_t col = cb * (int32_t)(blockDim.x >> 6) + w;
+    const int32_t col0 = (cb * (int32_t)(blockDim.x >> 6) + w) * CPW;
     const int lane = threadIdx.x & 63;
     const int32_t f = tile * kTile + lane;
     bool act = !done[f];
-    if (col >= n || !__any(act)) return;
+    if (col0 >= n || !__any(act)) return;
     const bool stop = act && test_now && unsat_cur[f] == 0u;
-    if (cb == 0 && w == 0) { // the wavefront of column 0 keeps the per-frame flags
+    if (col0 == 0) { // the wavefront of column 0 keeps the per-frame flags
         if (stop) {
             done[f] = 1u;
             conv[f] = t - 1;
@@ -259,24 +278,46 @@ __global__ __launch_bounds__(512) void k_bit(const int32_t *__restrict__ col_ptr
     act = act && !stop;
     if (!__any(act)) return;
     const float *et = eta + (size_t)tile * E * kTile + lane;
-    const int32_t k0 = col_ptr[col], k1 = col_ptr[col + 1];
-    const size_t o = ((size_t)tile * n + col) * kTile + lane;
-    const float rv = r[o];
-    float acc = 0.0f;
-    // Messages in groups of 8: every load of a group is issued before the
-    // first add, so a wavefront keeps up to 9 requests in flight instead of
-    // one; the adds still run in ascending check order.
-    for (int32_t k = k0; k < k1; k += 8) {
+    int32_t k0[CPW], k1[CPW];
+    float rv[CPW], acc[CPW], ev[CPW][8];
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+        const int32_t col = col0 + c < n ? col0 + c : col0;
+        k0[c] = col_ptr[col];
+        k1[c] = col0 + c < n ? col_ptr[col + 1] : k0[c]; // columns past n: no messages
+        rv[c] = r[((size_t)tile * n + col) * kTile + lane];
+    }
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
         int32_t idx[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) idx[u] = csc_edge[k + u]; // in bounds: the table has 8 entries of padding
-        float ev[8];
+        for (int u = 0; u < 8; ++u) idx[u] = csc_edge[k0[c] + u]; // in bounds: 8 entries of padding
+        const bool any = k1[c] > k0[c];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) ev[u] = et[(size_t)(k + u < k1 ? idx[u] : idx[0]) * kTile];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) acc = (k + u < k1) ? acc + ev[u] : acc; // a select, not a branch
+        for (int u = 0; u < 8; ++u)
+            ev[c][u] = any ? et[(size_t)(k0[c] + u < k1[c] ? idx[u] : idx[0]) * kTile] : 0.0f;
     }
-    if (act) s[o] = acc + rv;
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+        acc[c] = 0.0f;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[c] = (k0[c] + u < k1[c]) ? acc[c] + ev[c][u] : acc[c]; // a select
+        for (int32_t k = k0[c] + 8; k < k1[c]; k += 8) { // columns with more than 8 checks
+            int32_t idx[8];
+            float e2[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) idx[u] = csc_edge[k + u];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) e2[u] = et[(size_t)(k + u < k1[c] ? idx[u] : idx[0]) * kTile];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc[c] = (k + u < k1[c]) ? acc[c] + e2[u] : acc[c];
+        }
+    }
+    if (act) {
+#pragma unroll
+        for (int c = 0; c < CPW; ++c)
+            if (col0 + c < n) s[((size_t)tile * n + col0 + c) * kTile + lane] = acc[c] + rv[c];
+    }
 }
 
 // Syndrome of the current decision only (after the last iteration).
@@ -358,8 +399,9 @@ int stream_decode(const ldpc_graph &g, const float *llr, int32_t B, int32_t L, u
     const int32_t period = test_period(flags); // 0: no early exit
     // wavefronts per workgroup of the check / bit kernels (tuning record, else 4)
     const int32_t waves = (g.tuning.set && g.tuning.stream_waves > 0) ? g.tuning.stream_waves : 4;
-    const int32_t row_blocks = (g.m + waves - 1) / waves;
-    const int32_t col_blocks = (g.n + waves - 1) / waves;
+    const int32_t row_blocks = (g.m + waves - 1) / waves;                     // one row per wavefront
+    const int32_t row_blocks_dc = (g.m + waves * kRowsPerWave - 1) / (waves * kRowsPerWave);
+    const int32_t col_blocks = (g.n + waves * kColsPerWave - 1) / (waves * kColsPerWave);
     const int32_t nchunks = (g.n + 63) / 64;
     const int32_t ncls = (int32_t)g.class_degrees.size();
     // unrolled check kernel when every row has 6 or 7 edges
@@ -370,23 +412,23 @@ int stream_decode(const ldpc_graph &g, const float *llr, int32_t B, int32_t L, u
     for (int32_t t = 1; t <= L; ++t) {
         timed_launch(K_CHECK, stream, [&] {
             if (regular == 6)
-                k_check_dc<6><<<nt * row_blocks, 64 * waves, 0, stream>>>(g.col_idx, g.row_class, g.m, g.n, g.E,
-                                                                          row_blocks, w.r, w.s, w.eta, w.done,
-                                                                          w.unsat[t & 1], t, alpha, beta, ncls);
+                k_check_dc<6, kRowsPerWave><<<nt * row_blocks_dc, 64 * waves, 0, stream>>>(
+                    g.col_idx, g.row_class, g.m, g.n, g.E, row_blocks_dc, w.r, w.s, w.eta, w.done, w.unsat[t & 1], t,
+                    alpha, beta, ncls);
             else if (regular == 7)
-                k_check_dc<7><<<nt * row_blocks, 64 * waves, 0, stream>>>(g.col_idx, g.row_class, g.m, g.n, g.E,
-                                                                          row_blocks, w.r, w.s, w.eta, w.done,
-                                                                          w.unsat[t & 1], t, alpha, beta, ncls);
+                k_check_dc<7, kRowsPerWave><<<nt * row_blocks_dc, 64 * waves, 0, stream>>>(
+                    g.col_idx, g.row_class, g.m, g.n, g.E, row_blocks_dc, w.r, w.s, w.eta, w.done, w.unsat[t & 1], t,
+                    alpha, beta, ncls);
             else
                 k_check<<<nt * row_blocks, 64 * waves, 0, stream>>>(g.row_ptr, g.col_idx, g.row_class, g.m, g.n,
                                                                     g.E, B, row_blocks, w.r, w.s, w.eta, w.done,
                                                                     w.unsat[t & 1], t, alpha, beta, ncls);
         });
         timed_launch(K_BIT, stream, [&] {
-            k_bit<<<nt * col_blocks, 64 * waves, 0, stream>>>(g.col_ptr, g.csc_edge, g.n, g.E, col_blocks, w.r, w.s, w.eta,
-                                                       w.done, w.unsat[t & 1], w.unsat[(t + 1) & 1], w.conv, t,
-                                                       // is the decision of iteration t - 1 tested?
-                                                       (period > 0 && (t - 1) % period == 0) ? 1 : 0);
+            k_bit<kColsPerWave><<<nt * col_blocks, 64 * waves, 0, stream>>>(
+                g.col_ptr, g.csc_edge, g.n, g.E, col_blocks, w.r, w.s, w.eta, w.done, w.unsat[t & 1],
+                w.unsat[(t + 1) & 1], w.conv, t,
+                (period > 0 && (t - 1) % period == 0) ? 1 : 0); // is the decision of iteration t - 1 tested?
         });
     }
     uint32_t *unsat_final = w.unsat[(L + 1) & 1];

@@ -76,11 +76,20 @@ class NMSTrainer:
         self.history.append(loss.detach())
         return loss.detach()
 
-    def train(self, steps: int, log_every: int = 0, log=print):
+    def train(self, steps: int, log_every: int = 0, log=print, time_budget: float | None = None):
+        """Run `steps` Adam steps, or fewer if `time_budget` seconds run out
+        first (checked every 10 steps)."""
+        import time
+        t0 = time.time()
         for s in range(steps):
             loss = self.step()
             if log_every and (s + 1) % log_every == 0:
-                log(f"[nms] step {self.steps} loss {float(loss):.5f}")
+                log(f"[nms] step {self.steps} loss {float(loss):.5f} ({time.time() - t0:.1f} s)")
+            if time_budget is not None and (s + 1) % 10 == 0:
+                torch.cuda.synchronize()
+                if time.time() - t0 > time_budget:
+                    log(f"[nms] time budget reached after {s + 1} steps")
+                    break
         return self
 
     def state_dict(self):

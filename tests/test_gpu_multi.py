@@ -85,3 +85,29 @@ def test_multi_with_wide_variant_job(tdev):
         torch.cuda.synchronize()
         for x, y in zip(o, single):
             assert torch.equal(x, y)
+
+
+def test_multi_big_job_runs_alone(tdev):
+    """A batch large enough to fill the GPU on its own goes to a launch of its
+    own kernel inside the same call; outputs are unchanged."""
+    torch, dev = tdev
+    from paper_2507_10424_amd import ldpc
+    codes = [wl.regular_ldpc(96, 48, 3, 6, seed=1), wl.regular_ldpc(1024, 512, 3, 6, seed=2),
+             wl.random_irregular_code(300, 120, seed=3, dv_choices=(1, 2, 3, 4), max_row_degree=8)]
+    Bs = [300, 10000, 130]  # the n = 1024 job fills the GPU alone
+    jobs, inputs = [], []
+    for k, (H, B) in enumerate(zip(codes, Bs)):
+        llr = wl.bpsk_awgn_llr(None, 1.5, 0.5, seed=70 + k, n=H.shape[1], batch=B)
+        g = ldpc.build_graph(torch.from_numpy(H).to(dev))
+        jobs.append((g, torch.from_numpy(llr).to(dev)))
+        inputs.append((H, llr))
+    outs = ldpc.minsum_decode_multi(jobs, 30)
+    torch.cuda.synchronize()
+    for k, ((H, llr), o, (g, lt)) in enumerate(zip(inputs, outs, jobs)):
+        single = ldpc.minsum_decode(g, lt, 30)
+        torch.cuda.synchronize()
+        for x, y in zip(o, single):
+            assert torch.equal(x, y), f"job {k}"
+        sel = slice(0, min(llr.shape[0], 3000))
+        got = tuple(t[sel].cpu().numpy() for t in o)
+        assert_parity(got, oracle_decode(H, llr[sel], 30), f"big/small {k}")
