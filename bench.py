@@ -35,9 +35,9 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # 32-bit VALU lane-ops/s: 256 CUs x 64
 # changes the figure no longer applies and `traffic` is reported as null.
 # Summaries: profiles/hbm_bytes_qc64800_regular1024.md.
 MEASURED_TRAFFIC = {
-    ("regular1024", "onchip"): {"bytes": 608489285, "source": "decode_onchip.hip", "sha256_16": "e5ae54f2b205e750"},
-    ("qc64800", "check"): {"bytes": 10251460774, "source": "decode_stream.hip", "sha256_16": "05e9e4e489140852"},
-    ("qc64800", "bit"): {"bytes": 5691547662, "source": "decode_stream.hip", "sha256_16": "05e9e4e489140852"},
+    ("regular1024", "onchip"): {"bytes": 608454003, "source": "decode_onchip.hip", "sha256_16": "c57c852bfcb20c92"},
+    ("qc64800", "check"): {"bytes": 10301304363, "source": "decode_stream.hip", "sha256_16": "e635104923181df8"},
+    ("qc64800", "bit"): {"bytes": 5691632051, "source": "decode_stream.hip", "sha256_16": "e635104923181df8"},
 }
 
 
@@ -198,7 +198,7 @@ def main():
         log(f"[bench] tuning set: {tuning}")
     elif not args.no_autotune and args.path == "auto":
         ta = time.time()
-        tuning = ldpc.autotune(g, min(B, 16384), L, 2.0 if args.config != "qc64800" else 1.2)
+        tuning = ldpc.autotune(g, min(B, 65536), L, 2.0 if args.config != "qc64800" else 1.2)
         log(f"[bench] autotuned in {time.time() - ta:.1f} s: {tuning}")
     ws = torch.empty(max(1, ldpc.workspace_bytes(g, B, flags)), dtype=torch.uint8, device=dev)
     outs = [ldpc._outputs(B, n, dev, True) for _ in llrs]

@@ -308,9 +308,9 @@ int ldpc_graph_get_tuning(const ldpc_graph *g, ldpc_tuning *t);
  * warm-up and three decodes (at most max_iter iterations, early exit) for
  * every launch choice that applies to the graph (each fitting on-chip
  * variant, both register budgets, 0..4 workgroups per CU; the streaming path
- * with 1, 2, 4, 8 wavefronts per workgroup), and stores the fastest in the
- * graph's tuning
- * record (also returned in *best if non-null).  It synchronises `stream`
+ * with 1, 2, 4, 8 wavefronts per workgroup), times the four fastest again
+ * (three interleaved rounds of four decodes), and stores the fastest of those
+ * in the graph's tuning record (also returned in *best if non-null).  It synchronises `stream`
  * and creates two HIP events; do not capture it.  The workspace needs
  * ldpc_autotune_workspace_bytes(g, B) bytes.
  * Errors: LDPC_EINVAL, LDPC_EWORKSPACE, LDPC_EHIP.

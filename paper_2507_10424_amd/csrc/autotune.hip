@@ -8,6 +8,8 @@
 // 1, 2, 4 or 8 wavefronts per workgroup of its check and bit kernels.
 #include <vector>
 
+#include <algorithm>
+
 #include "ldpc_internal.h"
 
 namespace ldpc {
@@ -122,12 +124,11 @@ extern "C" int ldpc_autotune(ldpc_graph *g, int32_t B, int32_t max_iter, float e
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return LDPC_EHIP;
     const auto saved = g->tuning;
-    int best_k = -1;
-    float best_ms = 0.0f;
-    constexpr int kReps = 3;
-    for (size_t k = 0; k < cands.size() && st == LDPC_OK; ++k) {
-        st = ldpc_graph_set_tuning(g, &cands[k]);
-        if (st) break;
+    // Mean time of `reps` decodes with candidate k (after one untimed decode
+    // when `warm`), in ms, or a negative status.
+    auto time_cand = [&](size_t k, int reps, bool warm, float *ms_out) -> int {
+        int s2 = ldpc_graph_set_tuning(g, &cands[k]);
+        if (s2) return s2;
         auto run = [&]() {
             return cands[k].path == 1
                        ? onchip_decode(*g, w.llr, B, max_iter, 0, nullptr, nullptr, 0, w.bits, w.post, w.iters, w.ok,
@@ -135,21 +136,40 @@ extern "C" int ldpc_autotune(ldpc_graph *g, int32_t B, int32_t max_iter, float e
                        : stream_decode(*g, w.llr, B, max_iter, 0, nullptr, nullptr, 0, w.bits, w.post, w.iters, w.ok,
                                        w.dec, w.dec_bytes, stream);
         };
-        st = run(); // warm-up
-        if (st) break;
-        if (hipEventRecord(e0, stream) != hipSuccess) { st = LDPC_EHIP; break; }
-        for (int r = 0; r < kReps && st == LDPC_OK; ++r) st = run();
-        if (st) break;
+        if (warm && (s2 = run()) != LDPC_OK) return s2;
+        if (hipEventRecord(e0, stream) != hipSuccess) return LDPC_EHIP;
+        for (int r = 0; r < reps; ++r)
+            if ((s2 = run()) != LDPC_OK) return s2;
         float ms = 0.0f;
         if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-            st = LDPC_EHIP;
-            break;
-        }
-        cands[k].ms = ms / kReps;
-        if (best_k < 0 || cands[k].ms < best_ms) {
-            best_k = (int)k;
-            best_ms = cands[k].ms;
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+            return LDPC_EHIP;
+        *ms_out = ms / reps;
+        return LDPC_OK;
+    };
+    // First pass: every candidate, 3 timed decodes.  Second pass: the 4
+    // fastest again, 3 rounds of 4 decodes each, interleaved, so that drift of
+    // the clock or of other load hits them alike; the smallest total wins.
+    for (size_t k = 0; k < cands.size() && st == LDPC_OK; ++k) st = time_cand(k, 3, true, &cands[k].ms);
+    int best_k = -1;
+    if (st == LDPC_OK) {
+        std::vector<size_t> order(cands.size());
+        for (size_t k = 0; k < order.size(); ++k) order[k] = k;
+        std::sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cands[a].ms < cands[b].ms; });
+        const size_t top = order.size() < 4 ? order.size() : 4;
+        std::vector<float> total(top, 0.0f);
+        for (int round = 0; round < 3 && st == LDPC_OK; ++round)
+            for (size_t q = 0; q < top && st == LDPC_OK; ++q) {
+                float ms = 0.0f;
+                st = time_cand(order[q], 4, round == 0, &ms);
+                total[q] += ms;
+            }
+        if (st == LDPC_OK) {
+            size_t bq = 0;
+            for (size_t q = 1; q < top; ++q)
+                if (total[q] < total[bq]) bq = q;
+            best_k = (int)order[bq];
+            cands[best_k].ms = total[bq] / 3.0f;
         }
     }
     (void)hipEventDestroy(e0);
