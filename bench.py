@@ -110,6 +110,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-nms", action="store_true", help="skip the learned-decoder comparison")
     ap.add_argument("--no-dense", action="store_true", help="skip the dense (Algorithm 2) ablation")
+    ap.add_argument("--no-stream-alt", action="store_true",
+                    help="skip the streaming-path measurement of the n = 1024 workload")
     ap.add_argument("--profile-only", action="store_true", help="warmup + timed steps, no extras (for rocprofv3)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 256 MiB three times (calibrates the HBM byte counters of a profiler)")
@@ -314,6 +316,48 @@ def main():
             mism += int(np.any(gb != ob, axis=1).sum()) + int((gi != oi).sum())
         cpu["gpu_mismatches_on_sample"] = mism
 
+    # The same workload on the HBM-resident streaming path (one timed step),
+    # for its share of HBM bandwidth on this code.
+    stream_alt = None
+    if args.config == "regular1024" and args.path == "auto" and not args.no_stream_alt:
+        sflags = flags | ldpc.LDPC_FORCE_STREAM
+        sws = torch.empty(max(1, ldpc.workspace_bytes(g, B, sflags)), dtype=torch.uint8, device=dev)
+        souts = [ldpc._outputs(B, n, dev, True) for _ in llrs]
+
+        def sstep():
+            for x, o in zip(llrs, souts):
+                ldpc.minsum_decode(g, x, L, flags=sflags, workspace=sws, out=o)
+
+        sstep()
+        torch.cuda.synchronize()
+        lib.ldpc_timing_enable(1)
+        ev0.record()
+        sstep()
+        ev1.record()
+        torch.cuda.synchronize()
+        sms = ev0.elapsed_time(ev1)
+        st_k = {}
+        for kid, kname in [(0, "check"), (1, "bit")]:
+            ms_k, cnt = ctypes.c_double(), ctypes.c_int64()
+            lib.ldpc_timing_read(kid, ctypes.byref(ms_k), ctypes.byref(cnt))
+            st_k[kname] = (ms_k.value, cnt.value)
+        lib.ldpc_timing_enable(0)
+        sits = torch.cat([o[2].to(torch.int64) for o in souts]).to(torch.float64)
+        sbytes = float((sits * (12 * E + 12 * n)).sum() - (sits >= 1).double().sum() * 4 * E)
+        same = all(torch.equal(a[0], b[0]) and torch.equal(a[2], b[2]) for a, b in zip(souts, outs))
+        del sws
+        stream_alt = {"path": "stream", "coded_gbit_s": round(frames_step * n / (sms * 1e-3) / 1e9, 3),
+                      "ms_per_step": round(sms, 3),
+                      "hbm": {"achieved": round(sbytes / ((st_k["check"][0] + st_k["bit"][0]) * 1e-3) / 1e9, 1),
+                              "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": round(sbytes / ((st_k["check"][0] + st_k["bit"][0]) * 1e-3) / 1e9
+                                            / HBM_PEAK_GBS, 4),
+                              "note": "algorithmic bytes 12E + 12n per frame-iteration (4E less in iteration 1) "
+                                      "over the summed check and bit kernel time"},
+                      "outputs_equal_on_chip_path": bool(same)}
+        log(f"[bench] streaming path on the same workload: {stream_alt['coded_gbit_s']} Gbit/s, "
+            f"HBM frac {stream_alt['hbm']['frac']}")
+
     nms = dense = None
     try:
         if not args.no_nms:
@@ -334,7 +378,8 @@ def main():
                    "tuning": tuning},
         "edge_msg_per_s": edge_msgs, "info_gbit_s": round(gbits * k_info / n, 3) if k_info else None,
         "mean_iters": round(tot_iters / frames_step, 3), "per_point": per_point,
-        "roofline": roofline, "cpu_baseline": cpu, "nms_vs_plain": nms, "dense_ablation": dense,
+        "roofline": roofline, "cpu_baseline": cpu, "hbm_resident_path": stream_alt, "nms_vs_plain": nms,
+        "dense_ablation": dense,
     }
     print(json.dumps(line), flush=True)
 

@@ -116,8 +116,10 @@ extern "C" int ldpc_autotune(ldpc_graph *g, int32_t B, int32_t max_iter, float e
     std::vector<ldpc_tuning> cands;
     for (int v = 0; v < onchip_num_variants(); ++v) {
         if (!onchip_variant_fits(*g, v)) continue;
-        for (int wps : {0, 4})
+        for (int wps : {0, 4}) {
+            if (wps == 4 && !onchip_kernel_spill_free(v, 4)) continue; // the tighter budget spills: never faster
             for (int wpc : {0, 1, 2, 3, 4}) cands.push_back(ldpc_tuning{1, v, wpc, 4, wps, 0.0f});
+        }
     }
     for (int waves : {1, 2, 4, 8}) cands.push_back(ldpc_tuning{2, -1, 0, waves, 0, 0.0f});
 

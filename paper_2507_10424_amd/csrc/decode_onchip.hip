@@ -45,21 +45,27 @@
 namespace ldpc {
 namespace {
 
-constexpr int kF = 2; // frame slots per workgroup
-typedef float vf2 __attribute__((ext_vector_type(2)));
+constexpr int kMaxF = 4; // frame slots per workgroup: 2 or 4 (a kernel variant's choice)
+template <int F> struct Vec;
+template <> struct Vec<2> {
+    typedef float type __attribute__((ext_vector_type(2)));
+};
+template <> struct Vec<4> {
+    typedef float type __attribute__((ext_vector_type(4)));
+};
 
 struct Shared {          // small shared words, placed after s and eta
-    int32_t first[kF];   // first frame of each slot
-    int32_t next[kF][2]; // prefetched next frame of each slot, by refill parity
+    int32_t first[kMaxF];   // first frame of each slot
+    int32_t next[kMaxF][2]; // prefetched next frame of each slot, by refill parity
     uint32_t red[2];     // OR of the per-slot unsatisfied bits, by round parity
 };
 
-size_t state_bytes(const ldpc_graph &g) { return align_up(sizeof(vf2) * ((size_t)g.n + (size_t)g.E + 1), 16); }
-
-size_t onchip_lds_bytes(const ldpc_graph &g) {
-    // s[n] and eta[E + 1] (one padding slot) as float2, then Shared
-    return state_bytes(g) + sizeof(Shared);
+// s[n] and eta[E + 1] (one padding slot), F floats per entry, then Shared
+size_t state_bytes(const ldpc_graph &g, int F) {
+    return align_up(sizeof(float) * (size_t)F * ((size_t)g.n + (size_t)g.E + 1), 16);
 }
+
+size_t lds_bytes_for(const ldpc_graph &g, int F) { return state_bytes(g, F) + sizeof(Shared); }
 
 __global__ void k_zero_u32(uint32_t *p) { *p = 0u; }
 
@@ -119,11 +125,17 @@ template <int N> __device__ __forceinline__ void min_pair(const float *a, float 
     }
 }
 
-__device__ __forceinline__ vf2 lds_ld(const unsigned char *base, uint32_t off) {
-    return *reinterpret_cast<const vf2 *>(base + off);
+template <class V> __device__ __forceinline__ V lds_ld(const unsigned char *base, uint32_t off) {
+    return *reinterpret_cast<const V *>(base + off);
 }
-__device__ __forceinline__ void lds_st(unsigned char *base, uint32_t off, vf2 v) {
-    *reinterpret_cast<vf2 *>(base + off) = v;
+template <class V> __device__ __forceinline__ void lds_st(unsigned char *base, uint32_t off, V v) {
+    *reinterpret_cast<V *>(base + off) = v;
+}
+template <class V> __device__ __forceinline__ V vzero() {
+    V z;
+#pragma unroll
+    for (int q = 0; q < (int)(sizeof(V) / sizeof(float)); ++q) z[q] = 0.0f;
+    return z;
 }
 
 // One decoding job: a graph, its frames and outputs.
@@ -149,11 +161,13 @@ struct Job {
 // Decodes all frames of one job with the workgroup (see the file comment).
 // DC: row degree (RX: every row exactly DC, else at most DC); DV: column
 // degree (CX: every column exactly DV, else at most DV); RPT: rows per
-// thread; CPT: bits per thread (at most).  Every thread of the workgroup
-// calls it; it returns once all frames of the job handed to this workgroup
-// are done.
-template <int DC, bool RX, int DV, bool CX, int RPT, int CPT>
+// thread; CPT: bits per thread (at most); F: frame slots.  Every thread of
+// the workgroup calls it; it returns once all frames of the job handed to
+// this workgroup are done.
+template <int DC, bool RX, int DV, bool CX, int RPT, int CPT, int F>
 __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t early, unsigned char *lds) {
+    typedef typename Vec<F>::type V;
+    constexpr uint32_t kEnt = sizeof(V); // bytes of one LDS entry (F floats)
     const int32_t *__restrict__ row_ptr = J.row_ptr;
     const uint32_t *__restrict__ edge_tab = J.edge_tab;
     const int32_t *__restrict__ col_ptr = J.col_ptr;
@@ -170,7 +184,7 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
     const float *__restrict__ beta = J.beta;
     const int32_t ncls = J.ncls;
     uint32_t *__restrict__ queue = J.queue;
-    const uint32_t eta0 = (uint32_t)sizeof(vf2) * (uint32_t)n; // byte offset of eta
+    const uint32_t eta0 = kEnt * (uint32_t)n; // byte offset of eta
     Shared *sh = reinterpret_cast<Shared *>(lds + sh_off);
     const int tid = threadIdx.x;
     const int nt = blockDim.x;
@@ -189,8 +203,8 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
         for (int k = 0; k < DC; ++k) {
             const bool v = k < d;
             const uint32_t w = v ? edge_tab[e0 + k] : 0u;
-            sa[r][k] = (uint32_t)sizeof(vf2) * (w & 0xffffu);
-            ea[r][k] = eta0 + (uint32_t)sizeof(vf2) * (v ? (w >> 16) : (uint32_t)E); // padding slot
+            sa[r][k] = kEnt * (w & 0xffffu);
+            ea[r][k] = eta0 + kEnt * (v ? (w >> 16) : (uint32_t)E); // padding slot
         }
     }
     uint32_t ckd[CPT]; // first CSC slot | degree << 16 of each own bit
@@ -203,37 +217,37 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
 
     // ---- slots --------------------------------------------------------------
     if (tid == 0) {
-        const int32_t base = (int32_t)atomicAdd(queue, 2u * kF);
+        const int32_t base = (int32_t)atomicAdd(queue, 2u * F);
 #pragma unroll
-        for (int q = 0; q < kF; ++q) {
+        for (int q = 0; q < F; ++q) {
             sh->first[q] = base + q;
-            sh->next[q][0] = base + kF + q;
+            sh->next[q][0] = base + F + q;
         }
         sh->red[0] = sh->red[1] = 0u;
     }
     __syncthreads();
-    int32_t fr[kF], tt[kF], gen[kF], ph[kF]; // ph = (tt - 1) mod the test period
+    int32_t fr[F], tt[F], gen[F], ph[F]; // ph = (tt - 1) mod the test period
 #pragma unroll
-    for (int q = 0; q < kF; ++q) {
+    for (int q = 0; q < F; ++q) {
         fr[q] = __builtin_amdgcn_readfirstlane(sh->first[q]); // uniform: kept in scalar registers
         tt[q] = 1;
         gen[q] = 0;
         ph[q] = 0;
     }
-    vf2 eprev[RPT][DC];
-    vf2 rc[CPT];
+    V eprev[RPT][DC];
+    V rc[CPT];
 #pragma unroll
     for (int r = 0; r < RPT; ++r)
 #pragma unroll
-        for (int k = 0; k < DC; ++k) eprev[r][k] = vf2{0.0f, 0.0f};
+        for (int k = 0; k < DC; ++k) eprev[r][k] = vzero<V>();
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
         const int32_t j = tid + c * nt;
-        rc[c] = vf2{0.0f, 0.0f};
+        rc[c] = vzero<V>();
         if (j < n) {
 #pragma unroll
-            for (int q = 0; q < kF; ++q) rc[c][q] = fr[q] < B ? llr[(size_t)fr[q] * n + j] + 0.0f : 0.0f; // -0 -> +0
-            lds_st(lds, (uint32_t)sizeof(vf2) * (uint32_t)j, rc[c]);
+            for (int q = 0; q < F; ++q) rc[c][q] = fr[q] < B ? llr[(size_t)fr[q] * n + j] + 0.0f : 0.0f; // -0 -> +0
+            lds_st<V>(lds, kEnt * (uint32_t)j, rc[c]);
         }
     }
     __syncthreads();
@@ -242,7 +256,7 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
         // The slot state is the same in every lane; saying so keeps it in
         // scalar registers and makes the branches on it scalar.
 #pragma unroll
-        for (int q = 0; q < kF; ++q) {
+        for (int q = 0; q < F; ++q) {
             fr[q] = __builtin_amdgcn_readfirstlane(fr[q]);
             tt[q] = __builtin_amdgcn_readfirstlane(tt[q]);
             gen[q] = __builtin_amdgcn_readfirstlane(gen[q]);
@@ -250,7 +264,7 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
         }
         bool live = false;
 #pragma unroll
-        for (int q = 0; q < kF; ++q) live |= fr[q] < B;
+        for (int q = 0; q < F; ++q) live |= fr[q] < B;
         if (!live) break;
 
         // ---- check pass -------------------------------------------------------
@@ -259,11 +273,11 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
         for (int r = 0; r < RPT; ++r) {
             const int32_t d = RX ? DC : deg[r];
             const bool rowv = RX ? (tid + r * nt < m) : deg[r] > 0; // RX: recomputed, saves a register
-            vf2 sv[DC];
+            V sv[DC];
 #pragma unroll
-            for (int k = 0; k < DC; ++k) sv[k] = lds_ld(lds, sa[r][k]);
+            for (int k = 0; k < DC; ++k) sv[k] = lds_ld<V>(lds, sa[r][k]);
 #pragma unroll
-            for (int q = 0; q < kF; ++q) {
+            for (int q = 0; q < F; ++q) {
                 // RX: every edge of a real row is valid; rows past m compute
                 // garbage that only reaches the padding slot and is masked
                 // out of the syndrome.  Otherwise edges k >= d are masked.
@@ -310,14 +324,14 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
             }
 #pragma unroll
             for (int k = 0; k < DC; ++k)
-                if (RX || k < d) lds_st(lds, ea[r][k], eprev[r][k]); // rows past m write the padding slot
+                if (RX || k < d) lds_st<V>(lds, ea[r][k], eprev[r][k]); // rows past m write the padding slot
         }
 
         // ---- per-slot syndrome over the workgroup ------------------------------
         const int p = round & 1;
         uint32_t wm = 0;
 #pragma unroll
-        for (int q = 0; q < kF; ++q) wm |= (__ballot((umask >> q) & 1u) != 0ull ? 1u : 0u) << q;
+        for (int q = 0; q < F; ++q) wm |= (__ballot((umask >> q) & 1u) != 0ull ? 1u : 0u) << q;
         if ((tid & 63) == 0 && wm) atomicOr(&sh->red[p], wm);
         __syncthreads();
         const uint32_t U = __builtin_amdgcn_readfirstlane(sh->red[p]);
@@ -326,7 +340,7 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
         // ---- decisions, outputs, refills --------------------------------------
         uint32_t fin = 0;
 #pragma unroll
-        for (int q = 0; q < kF; ++q) {
+        for (int q = 0; q < F; ++q) {
             if (fr[q] >= B) continue;
             // a codeword test is due when the decision's iteration tt - 1 is
             // a multiple of the period (early = 0: never)
@@ -338,7 +352,7 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
             for (int c = 0; c < CPT; ++c) {
                 const int32_t j = tid + c * nt;
                 if (j < n) {
-                    const float v = lds_ld(lds, (uint32_t)sizeof(vf2) * (uint32_t)j)[q];
+                    const float v = lds_ld<V>(lds, kEnt * (uint32_t)j)[q];
                     if (post) post[(size_t)f * n + j] = v;
                     bits[(size_t)f * n + j] = v < 0.0f ? 1 : 0;
                 }
@@ -366,30 +380,30 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
             if (j < n) {
                 // CX: every bit has DV slots, so bit j's first slot is DV j
                 const uint32_t base =
-                    eta0 + (uint32_t)sizeof(vf2) * (CX ? (uint32_t)(DV * j) : (ckd[c] & 0xffffu));
+                    eta0 + kEnt * (CX ? (uint32_t)(DV * j) : (ckd[c] & 0xffffu));
                 const int32_t dv = CX ? DV : (int32_t)(ckd[c] >> 16);
-                vf2 ev[DV];
+                V ev[DV];
 #pragma unroll
                 for (int k = 0; k < DV; ++k)
-                    ev[k] = lds_ld(lds, base + (uint32_t)sizeof(vf2) * (uint32_t)(CX || k < dv ? k : 0));
-                vf2 acc = (CX || 0 < dv) ? ev[0] : vf2{0.0f, 0.0f};
+                    ev[k] = lds_ld<V>(lds, base + kEnt * (uint32_t)(CX || k < dv ? k : 0));
+                V acc = (CX || 0 < dv) ? ev[0] : vzero<V>();
 #pragma unroll
                 for (int k = 1; k < DV; ++k)
-                    acc = acc + ((CX || k < dv) ? ev[k] : vf2{0.0f, 0.0f}); // +0 adds change no s
-                vf2 sn = acc + rc[c];
+                    acc = acc + ((CX || k < dv) ? ev[k] : vzero<V>()); // +0 adds change no s
+                V sn = acc + rc[c];
 #pragma unroll
-                for (int q = 0; q < kF; ++q) {
+                for (int q = 0; q < F; ++q) {
                     if ((fin >> q) & 1u) {
                         const float v = fr[q] < B ? llr[(size_t)fr[q] * n + j] + 0.0f : 0.0f;
                         rc[c][q] = v;
                         sn[q] = v;
                     }
                 }
-                lds_st(lds, (uint32_t)sizeof(vf2) * (uint32_t)j, sn);
+                lds_st<V>(lds, kEnt * (uint32_t)j, sn);
             }
         }
 #pragma unroll
-        for (int q = 0; q < kF; ++q) {
+        for (int q = 0; q < F; ++q) {
             const bool refilled = (fin >> q) & 1u;
             tt[q] = refilled ? 1 : tt[q] + 1;
             ph[q] = (refilled || ph[q] + 1 == early) ? 0 : ph[q] + 1;
@@ -407,19 +421,24 @@ struct Variant {
     bool cx;
     int rpt;
     int cpt;
+    int f; // frame slots per workgroup
 };
 
-// Exact-degree variants for the regular codes in use first, then masked ones.
-// The order is the dispatch order of pick below.
+// Exact-degree variants for the regular codes in use first, then masked ones,
+// then four-slot variants of the (3,6) shape (float4 LDS entries: half the
+// LDS instructions and per-frame loop work per frame, twice the LDS per
+// workgroup).  The order is the dispatch order of pick below.
 constexpr Variant kVariants[] = {
-    {6, true, 3, true, 2, 4},   {6, true, 8, false, 2, 4},  {9, true, 8, false, 2, 8},   {12, true, 8, false, 1, 4},
-    {16, true, 8, false, 1, 8}, {8, false, 8, false, 2, 4}, {16, false, 16, false, 1, 8}, {6, true, 3, true, 1, 4},
+    {6, true, 3, true, 2, 4, 2},   {6, true, 8, false, 2, 4, 2},  {9, true, 8, false, 2, 8, 2},
+    {12, true, 8, false, 1, 4, 2}, {16, true, 8, false, 1, 8, 2}, {8, false, 8, false, 2, 4, 2},
+    {16, false, 16, false, 1, 8, 2}, {6, true, 3, true, 1, 4, 2}, {6, true, 3, true, 2, 4, 4},
+    {6, true, 3, true, 1, 4, 4},
 };
 constexpr int kNumVariants = (int)(sizeof(kVariants) / sizeof(kVariants[0]));
 
 template <int V> __device__ __forceinline__ void run_v(const Job &J, int32_t L, int32_t early, unsigned char *lds) {
     constexpr Variant v = kVariants[V];
-    run_onchip<v.dc, v.rx, v.dv, v.cx, v.rpt, v.cpt>(J, L, early, lds);
+    run_onchip<v.dc, v.rx, v.dv, v.cx, v.rpt, v.cpt, v.f>(J, L, early, lds);
 }
 
 
@@ -446,7 +465,7 @@ struct JobTable {
 // alone would push every variant of the launch into spills.  Jobs that need
 // it get a launch of their own.
 constexpr int kWideVariant = 6;
-static_assert(kNumVariants == 8, "k_onchip_multi dispatches variants 0-5 and 7");
+static_assert(kNumVariants == 10, "k_onchip_multi dispatches variants 0-5 and 7-9");
 
 __global__ __launch_bounds__(kMaxThreads) void k_onchip_multi(const JobTable jt, int32_t L, int32_t early) {
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
@@ -459,6 +478,8 @@ __global__ __launch_bounds__(kMaxThreads) void k_onchip_multi(const JobTable jt,
         case 4: run_v<4>(jt.job[c], L, early, lds); break;
         case 5: run_v<5>(jt.job[c], L, early, lds); break;
         case 7: run_v<7>(jt.job[c], L, early, lds); break;
+        case 8: run_v<8>(jt.job[c], L, early, lds); break;
+        case 9: run_v<9>(jt.job[c], L, early, lds); break;
         default: break; // the host never places kWideVariant here
         }
         __syncthreads();
@@ -466,11 +487,11 @@ __global__ __launch_bounds__(kMaxThreads) void k_onchip_multi(const JobTable jt,
 }
 
 using KernelFn = void (*)(const Job, int32_t, int32_t);
-const KernelFn kKernels[2][8] = {
+const KernelFn kKernels[2][kNumVariants] = {
     {&k_onchip<0, 0>, &k_onchip<1, 0>, &k_onchip<2, 0>, &k_onchip<3, 0>, &k_onchip<4, 0>, &k_onchip<5, 0>,
-     &k_onchip<6, 0>, &k_onchip<7, 0>},
+     &k_onchip<6, 0>, &k_onchip<7, 0>, &k_onchip<8, 0>, &k_onchip<9, 0>},
     {&k_onchip<0, 4>, &k_onchip<1, 4>, &k_onchip<2, 4>, &k_onchip<3, 4>, &k_onchip<4, 4>, &k_onchip<5, 4>,
-     &k_onchip<6, 4>, &k_onchip<7, 4>}};
+     &k_onchip<6, 4>, &k_onchip<7, 4>, &k_onchip<8, 4>, &k_onchip<9, 4>}};
 
 // Threads: whole wavefronts, enough for RPT rows and CPT bits per thread.
 int threads_for(const ldpc_graph &g, const Variant &v) {
@@ -485,8 +506,11 @@ bool variant_ok(const ldpc_graph &g, int k) {
     const Variant &v = kVariants[k];
     const bool rows_ok = v.rx ? (g.dc_min == v.dc && g.dc_max == v.dc) : g.dc_max <= v.dc;
     const bool cols_ok = v.cx ? (g.dv_min == v.dv && g.dv_max == v.dv) : g.dv_max <= v.dv;
-    return rows_ok && cols_ok && threads_for(g, v) <= kMaxThreads;
+    return rows_ok && cols_ok && threads_for(g, v) <= kMaxThreads && g.edge_tab != nullptr &&
+           lds_bytes_for(g, v.f) + 1024 <= (size_t)g.lds_max;
 }
+
+size_t lds_of(const ldpc_graph &g, int variant) { return lds_bytes_for(g, kVariants[variant].f); }
 
 // The tuned variant if one is set and valid, else the first that fits.
 int pick(const ldpc_graph &g) {
@@ -506,7 +530,7 @@ Job make_job(const ldpc_graph &g, int variant, const float *llr, int32_t B, uint
     J.m = g.m;
     J.n = g.n;
     J.E = (int32_t)g.E;
-    J.sh_off = (uint32_t)state_bytes(g);
+    J.sh_off = (uint32_t)state_bytes(g, kVariants[variant].f);
     J.llr = llr;
     J.B = B;
     J.bits = bits;
@@ -527,14 +551,15 @@ __global__ void k_zero_words(uint32_t *p, int32_t count) {
 }
 
 // Grid of a persistent launch: every CU filled to its occupancy, but no more
-// workgroups than there are groups of 2 * kF frames.
-int launch_grid(const void *fn, int threads, size_t lds, int num_cu, int64_t frames, int cap_per_cu, int *grid) {
+// workgroups than there are groups of 2 F frames.
+int launch_grid(const void *fn, int threads, size_t lds, int num_cu, int64_t frames, int cap_per_cu, int *grid,
+                int F = 2) {
     if (hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess) return LDPC_EHIP;
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, lds) != hipSuccess) return LDPC_EHIP;
     if (cap_per_cu > 0 && per_cu > cap_per_cu) per_cu = cap_per_cu;
     per_cu = per_cu < 1 ? 1 : per_cu;
-    const int64_t groups = (frames + 2 * kF - 1) / (2 * kF);
+    const int64_t groups = (frames + 2 * F - 1) / (2 * F);
     const int64_t want = (int64_t)num_cu * per_cu;
     *grid = (int)(want < groups ? want : groups);
     if (*grid < 1) *grid = 1;
@@ -543,15 +568,19 @@ int launch_grid(const void *fn, int threads, size_t lds, int num_cu, int64_t fra
 
 } // namespace
 
-bool onchip_fits(const ldpc_graph &g) {
-    return g.edge_tab != nullptr && pick(g) >= 0 && onchip_lds_bytes(g) + 1024 <= (size_t)g.lds_max;
-}
+bool onchip_fits(const ldpc_graph &g) { return g.edge_tab != nullptr && pick(g) >= 0; }
 
-bool onchip_variant_fits(const ldpc_graph &g, int variant) {
-    return g.edge_tab != nullptr && variant_ok(g, variant) && onchip_lds_bytes(g) + 1024 <= (size_t)g.lds_max;
-}
+bool onchip_variant_fits(const ldpc_graph &g, int variant) { return variant_ok(g, variant); }
 
 int onchip_num_variants() { return kNumVariants; }
+
+bool onchip_kernel_spill_free(int variant, int waves_per_simd) {
+    if (variant < 0 || variant >= kNumVariants) return false;
+    hipFuncAttributes a{};
+    if (hipFuncGetAttributes(&a, (const void *)kKernels[waves_per_simd == 4 ? 1 : 0][variant]) != hipSuccess)
+        return false;
+    return a.localSizeBytes == 0;
+}
 
 size_t onchip_workspace_bytes(const ldpc_graph &g, int32_t B) {
     (void)g;
@@ -568,9 +597,10 @@ int onchip_decode(const ldpc_graph &g, const float *llr, int32_t B, int32_t L, u
     const int v = pick(g);
     const KernelFn fn = kKernels[(g.tuning.set && g.tuning.waves_per_simd == 4) ? 1 : 0][v];
     const int threads = threads_for(g, kVariants[v]);
-    const size_t lds = onchip_lds_bytes(g);
+    const size_t lds = lds_of(g, v);
     int grid = 0;
-    int st = launch_grid((const void *)fn, threads, lds, g.num_cu, B, g.tuning.set ? g.tuning.wg_per_cu : 0, &grid);
+    int st = launch_grid((const void *)fn, threads, lds, g.num_cu, B, g.tuning.set ? g.tuning.wg_per_cu : 0, &grid,
+                         kVariants[v].f);
     if (st) return st;
     uint32_t *queue = (uint32_t *)ws;
     const int32_t early = test_period(flags);
@@ -628,7 +658,7 @@ int onchip_decode_multi(const ldpc_job *jobs, int32_t njobs, int32_t L, uint32_t
                 }
         const KernelFn fn = kKernels[(g.tuning.set && g.tuning.waves_per_simd == 4) ? 1 : 0][v_own];
         const int t_own = threads_for(g, kVariants[v_own]);
-        const size_t l_own = onchip_lds_bytes(g);
+        const size_t l_own = lds_of(g, v_own);
         bool alone = v == kWideVariant;
         if (!alone) {
             int per_cu = 0;
@@ -636,7 +666,7 @@ int onchip_decode_multi(const ldpc_job *jobs, int32_t njobs, int32_t L, uint32_t
                     hipSuccess ||
                 hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void *)fn, t_own, l_own) != hipSuccess)
                 return LDPC_EHIP;
-            const int64_t in_flight = (int64_t)(per_cu < 1 ? 1 : per_cu) * g.num_cu * kF;
+            const int64_t in_flight = (int64_t)(per_cu < 1 ? 1 : per_cu) * g.num_cu * kVariants[v_own].f;
             alone = (int64_t)jb.B >= kOwnLaunchRounds * in_flight;
         }
         if (alone) {
@@ -647,7 +677,7 @@ int onchip_decode_multi(const ldpc_job *jobs, int32_t njobs, int32_t L, uint32_t
         }
         const int t = threads_for(g, kVariants[v]);
         threads = t > threads ? t : threads;
-        lds = onchip_lds_bytes(g) > lds ? onchip_lds_bytes(g) : lds;
+        lds = lds_of(g, v) > lds ? lds_of(g, v) : lds;
         frames += jb.B;
         num_cu = g.num_cu;
         jt.job[nj++] = make_job(g, v, jb.llr_dev, jb.B, jb.bits_dev, jb.post_dev, jb.iters_dev, jb.ok_dev, nullptr,
@@ -659,7 +689,8 @@ int onchip_decode_multi(const ldpc_job *jobs, int32_t njobs, int32_t L, uint32_t
     k_zero_words<<<1, 64, 0, stream>>>(queues, njobs);
     for (const Own &o : own) {
         int grid = 0;
-        const int st = launch_grid((const void *)o.fn, o.threads, o.lds, o.num_cu, o.J.B, 0, &grid);
+        const int st = launch_grid((const void *)o.fn, o.threads, o.lds, o.num_cu, o.J.B, 0, &grid,
+                                   kVariants[o.J.variant].f);
         if (st) return st;
         const Job J = o.J;
         const KernelFn fn = o.fn;

@@ -63,6 +63,8 @@ int stream_decode(const ldpc_graph &g, const float *llr, int32_t B, int32_t L, u
 bool onchip_fits(const ldpc_graph &g);
 bool onchip_variant_fits(const ldpc_graph &g, int variant);
 int onchip_num_variants();
+// Whether the kernel of (variant, register budget) needs no scratch (no spills).
+bool onchip_kernel_spill_free(int variant, int waves_per_simd);
 size_t onchip_workspace_bytes(const ldpc_graph &g, int32_t B);
 int onchip_decode(const ldpc_graph &g, const float *llr, int32_t B, int32_t L, uint32_t flags,
                   const float *alpha, const float *beta, int32_t T, uint8_t *bits, float *post,

@@ -186,3 +186,29 @@ def test_paths_agree_and_auto_choice():
     g = ldpc.build_graph(torch.from_numpy(H).cuda())
     assert ldpc.workspace_bytes(g, 500) == ldpc.workspace_bytes(g, 500, ldpc.LDPC_FORCE_ONCHIP)
     assert ldpc.workspace_bytes(g, 500) < ldpc.workspace_bytes(g, 500, ldpc.LDPC_FORCE_STREAM)
+
+
+@pytest.mark.parametrize("path", sorted(PATHS))
+def test_largest_onchip_regular_code(path):
+    """(3,6) code n = 2048: 512 threads of two rows and four bits each and
+    65 KB of LDS state, the largest (3,6) code the on-chip path takes; the
+    streaming path decodes the same frames."""
+    H = wl.regular_ldpc(2048, 1024, 3, 6, seed=8)
+    llr = wl.bpsk_awgn_llr(None, 1.75, 0.5, seed=88, n=2048, batch=300)
+    check(H, llr, 40, PATHS[path], what=f"n=2048 {path}")
+
+
+def test_onchip_refuses_too_many_threads():
+    """n = 4096 needs 1024 threads of two rows: the on-chip path reports
+    LDPC_EUNSUPPORTED when forced, and the automatic choice streams."""
+    import torch
+    from paper_2507_10424_amd import ldpc
+    H = wl.regular_ldpc(4096, 2048, 3, 6, seed=9)
+    g = ldpc.build_graph(torch.from_numpy(H).to("cuda:0"))
+    x = torch.from_numpy(wl.bpsk_awgn_llr(None, 2.0, 0.5, seed=9, n=4096, batch=70)).to("cuda:0")
+    with pytest.raises(ldpc.LdpcError) as e:
+        ldpc.minsum_decode(g, x, 10, flags=PATHS["onchip"])
+    assert e.value.status == -6
+    out = ldpc.minsum_decode(g, x, 10)
+    torch.cuda.synchronize()
+    assert_parity(tuple(t.cpu().numpy() for t in out), oracle_decode(H, x.cpu().numpy(), 10), "n=4096 auto")

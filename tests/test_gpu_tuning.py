@@ -28,7 +28,7 @@ def test_all_launch_choices_agree(tdev):
     llr = torch.from_numpy(llr_np).to(dev)
     ref = oracle_decode(H, llr_np, 40)
     tried = 0
-    for v, wpc, wps in itertools.product(range(8), (0, 1, 3), (0, 4)):
+    for v, wpc, wps in itertools.product(range(10), (0, 1, 3), (0, 4)):
         try:
             ldpc.set_tuning(g, 1, variant=v, wg_per_cu=wpc, waves_per_simd=wps)
         except ldpc.LdpcError as e:
@@ -60,3 +60,21 @@ def test_autotune_keeps_valid_choice(tdev):
     out = ldpc.minsum_decode(g, torch.from_numpy(llr_np).to(dev), 20)
     torch.cuda.synchronize()
     assert_parity(tuple(t.cpu().numpy() for t in out), oracle_decode(H, llr_np, 20), "autotuned")
+
+
+@pytest.mark.parametrize("B", [1, 3, 4, 5, 130, 777])
+def test_four_slot_variants_ragged(tdev, B):
+    """The four-slot variants (float4 LDS state) refill each slot on its own;
+    batches that leave slots empty or uneven must decode like the oracle."""
+    torch, dev = tdev
+    from paper_2507_10424_amd import ldpc
+    H = wl.regular_ldpc(96, 48, 3, 6, seed=1)
+    g = ldpc.build_graph(torch.from_numpy(H).to(dev))
+    llr_np = wl.bpsk_awgn_llr(None, 1.5, 0.5, seed=500 + B, n=96, batch=B)
+    ref = oracle_decode(H, llr_np, 25)
+    for v in (8, 9):
+        for wpc in (0, 1):
+            ldpc.set_tuning(g, 1, variant=v, wg_per_cu=wpc)
+            out = ldpc.minsum_decode(g, torch.from_numpy(llr_np).to(dev), 25)
+            torch.cuda.synchronize()
+            assert_parity(tuple(t.cpu().numpy() for t in out), ref, f"variant {v} wpc {wpc} B {B}")
