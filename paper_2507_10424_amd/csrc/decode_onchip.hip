@@ -1,21 +1,21 @@
 // On-chip Min-Sum decoder: the whole decoding state of a frame lives in LDS
 // and registers, for codes whose state fits (n, E < 2^16, row and column
-// degrees <= 16, at most 1024 threads of <= 2 rows and <= 8 bits each, state
+// degrees <= 16, at most 512 threads of <= 2 rows and <= 8 bits each, state
 // within one workgroup's LDS).
 //
-// Workgroups are persistent.  Each holds F = 2 frame "slots" and decodes
-// both in lock step, one iteration per round; a slot whose frame stops takes
-// the next frame number from an atomic counter at once, so per-frame early
-// exit wastes no rounds and the graph is read from global memory only once
-// per workgroup.
+// Workgroups are persistent.  Each holds F frame "slots" (F = 2 or 4, a
+// choice of the kernel variant) and decodes them in lock step, one iteration
+// per round; a slot whose frame stops takes the next frame number from an
+// atomic counter at once, so per-frame early exit wastes no rounds and the
+// graph is read from global memory only once per workgroup.
 //
 // Ownership.  Thread `tid` owns check rows tid + r*nt (r < RPT) and bits
 // tid + c*nt (c < CPT).  It keeps in registers, for the whole launch, the LDS
 // byte addresses of its edges' s and eta entries, and per slot the messages
 // it sent along its edges in the previous iteration (eta_prev) and the
-// channel LLRs of its bits.  LDS holds, per bit, s of both slots (float2) and,
-// per edge in CSC order, the current messages of both slots (float2), so one
-// 8-byte LDS access serves both frames.
+// channel LLRs of its bits.  LDS holds, per bit, s of all slots (F floats)
+// and, per edge in CSC order, the current messages of all slots (F floats),
+// so one 8- or 16-byte LDS access serves all F frames.
 //
 // Round (iteration t of each slot):
 //   check pass  per own row and slot: x_e = s_j - eta_prev_e; min0/min1 of

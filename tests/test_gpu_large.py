@@ -17,13 +17,30 @@ def dev():
     return torch.device("cuda:0")
 
 
-def _decode_full(H, llr_t, L, flags=0):
+def _decode_full(H, llr_t, L, tune_ebn0, flags=0):
+    """Autotune on the full batch as bench.py does, then decode with the
+    chosen launch configuration."""
     import torch
     from paper_2507_10424_amd import ldpc
     g = ldpc.build_graph(torch.from_numpy(H).to(llr_t.device))
+    tuning = ldpc.autotune(g, min(llr_t.shape[0], 65536), L, tune_ebn0)
+    note(f"[large] tuned launch: {tuning}")
     out = ldpc.minsum_decode(g, llr_t, L, flags=flags)
     torch.cuda.synchronize()
     return [t.cpu().numpy() for t in out]
+
+
+def _check_all_frames(H, out, L):
+    """Properties every frame must have at any size: iterations within
+    [0, L]; a frame that stopped early is a codeword; the flag is the
+    codeword test of the returned decision; bits are the slicer of post."""
+    import scipy.sparse as sp
+    gb, gp, gi, go = out
+    assert gi.min() >= 0 and gi.max() <= L
+    assert np.all(go[gi < L] == 1)
+    syn = (sp.csr_matrix(H.astype(np.int32)) @ gb.T.astype(np.int32)) % 2  # m x B, by a sparse product
+    assert np.array_equal(go == 1, ~np.asarray(syn).any(axis=0))
+    assert np.array_equal(gb, (gp < 0).astype(np.uint8))
 
 
 def _sample(iters, k, rng):
@@ -40,7 +57,8 @@ def test_regular1024_full_batch(dev):
     enc = wl.gf2_encoder(H)
     cw = enc.random_codewords_torch(65536, 202, dev)
     llr = wl.bpsk_awgn_llr_torch(cw, 2.0, 0.5, 302, dev)
-    gb, gp, gi, go = _decode_full(H, llr, 50)
+    gb, gp, gi, go = _decode_full(H, llr, 50, 2.0)
+    _check_all_frames(H, (gb, gp, gi, go), 50)
     idx = _sample(gi, 192, np.random.default_rng(0))
     note(f"[large] n=1024 full batch, checking {idx.size} frames, mean iters {gi.mean():.2f}")
     ref = oracle_decode(H, llr.cpu().numpy()[idx], 50)
@@ -52,7 +70,8 @@ def test_qc64800_full_batch(dev, ebn0):
     """Irregular QC n=64800, 4096 all-zero frames, L=50 (streaming path)."""
     H = wl.large_qc_code(seed=5)
     llr = wl.bpsk_awgn_llr_torch(None, ebn0, 0.5, 500, dev, n=H.shape[1], batch=4096)
-    gb, gp, gi, go = _decode_full(H, llr, 50)
+    gb, gp, gi, go = _decode_full(H, llr, 50, 1.2)
+    _check_all_frames(H, (gb, gp, gi, go), 50)
     idx = _sample(gi, 4, np.random.default_rng(1))
     note(f"[large] n=64800 at {ebn0} dB, checking frames {idx.tolist()}, mean iters {gi.mean():.2f}")
     ref = oracle_decode(H, llr.cpu().numpy()[idx], 50)
