@@ -164,7 +164,9 @@ struct Job {
 // thread; CPT: bits per thread (at most); F: frame slots.  Every thread of
 // the workgroup calls it; it returns once all frames of the job handed to
 // this workgroup are done.
-template <int DC, bool RX, int DV, bool CX, int RPT, int CPT, int F>
+// NMS: the learned check update (J.alpha, J.beta non-null); plain Min-Sum
+// instantiations carry no trace of it.
+template <int DC, bool RX, int DV, bool CX, int RPT, int CPT, int F, bool NMS>
 __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t early, unsigned char *lds) {
     typedef typename Vec<F>::type V;
     constexpr uint32_t kEnt = sizeof(V); // bytes of one LDS entry (F floats)
@@ -198,7 +200,7 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
         const int32_t e0 = i < m ? row_ptr[i] : 0;
         const int32_t d = i < m ? row_ptr[i + 1] - e0 : 0;
         deg[r] = d;
-        rcls[r] = (i < m && alpha != nullptr) ? row_class[i] : 0;
+        rcls[r] = (NMS && i < m) ? row_class[i] : 0;
 #pragma unroll
         for (int k = 0; k < DC; ++k) {
             const bool v = k < d;
@@ -303,7 +305,7 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
                 if (RX && !rowv) syn = 0u;
                 umask |= (syn >> 31) << q;
                 uint32_t b0 = __float_as_uint(mn0), b1 = __float_as_uint(mn1);
-                if (alpha != nullptr) {
+                if (NMS) {
                     if (tt[q] <= L && rowv) {
                         const float al = alpha[(tt[q] - 1) * ncls + rcls[r]];
                         const float be = beta[(tt[q] - 1) * ncls + rcls[r]];
@@ -436,20 +438,21 @@ constexpr Variant kVariants[] = {
 };
 constexpr int kNumVariants = (int)(sizeof(kVariants) / sizeof(kVariants[0]));
 
-template <int V> __device__ __forceinline__ void run_v(const Job &J, int32_t L, int32_t early, unsigned char *lds) {
+template <int V, bool NMS>
+__device__ __forceinline__ void run_v(const Job &J, int32_t L, int32_t early, unsigned char *lds) {
     constexpr Variant v = kVariants[V];
-    run_onchip<v.dc, v.rx, v.dv, v.cx, v.rpt, v.cpt, v.f>(J, L, early, lds);
+    run_onchip<v.dc, v.rx, v.dv, v.cx, v.rpt, v.cpt, v.f, NMS>(J, L, early, lds);
 }
 
 
 // One graph per launch, one variant instantiated.  W > 0 asks the compiler
 // for at least W waves per SIMD (fewer registers per thread, more resident
 // waves to hide LDS latency); W = 0 leaves the register budget to it.
-template <int V, int W>
+template <int V, int W, bool NMS>
 __global__ __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(W > 0 ? W : 1))) void k_onchip(
     const Job J, int32_t L, int32_t early) {
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
-    run_v<V>(J, L, early, lds);
+    run_v<V, NMS>(J, L, early, lds);
 }
 
 // Several graphs in one launch: every workgroup works through the jobs in
@@ -471,15 +474,15 @@ __global__ __launch_bounds__(kMaxThreads) void k_onchip_multi(const JobTable jt,
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
     for (int32_t c = 0; c < jt.njobs; ++c) {
         switch (jt.job[c].variant) {
-        case 0: run_v<0>(jt.job[c], L, early, lds); break;
-        case 1: run_v<1>(jt.job[c], L, early, lds); break;
-        case 2: run_v<2>(jt.job[c], L, early, lds); break;
-        case 3: run_v<3>(jt.job[c], L, early, lds); break;
-        case 4: run_v<4>(jt.job[c], L, early, lds); break;
-        case 5: run_v<5>(jt.job[c], L, early, lds); break;
-        case 7: run_v<7>(jt.job[c], L, early, lds); break;
-        case 8: run_v<8>(jt.job[c], L, early, lds); break;
-        case 9: run_v<9>(jt.job[c], L, early, lds); break;
+        case 0: run_v<0, false>(jt.job[c], L, early, lds); break;
+        case 1: run_v<1, false>(jt.job[c], L, early, lds); break;
+        case 2: run_v<2, false>(jt.job[c], L, early, lds); break;
+        case 3: run_v<3, false>(jt.job[c], L, early, lds); break;
+        case 4: run_v<4, false>(jt.job[c], L, early, lds); break;
+        case 5: run_v<5, false>(jt.job[c], L, early, lds); break;
+        case 7: run_v<7, false>(jt.job[c], L, early, lds); break;
+        case 8: run_v<8, false>(jt.job[c], L, early, lds); break;
+        case 9: run_v<9, false>(jt.job[c], L, early, lds); break;
         default: break; // the host never places kWideVariant here
         }
         __syncthreads();
@@ -487,11 +490,13 @@ __global__ __launch_bounds__(kMaxThreads) void k_onchip_multi(const JobTable jt,
 }
 
 using KernelFn = void (*)(const Job, int32_t, int32_t);
-const KernelFn kKernels[2][kNumVariants] = {
-    {&k_onchip<0, 0>, &k_onchip<1, 0>, &k_onchip<2, 0>, &k_onchip<3, 0>, &k_onchip<4, 0>, &k_onchip<5, 0>,
-     &k_onchip<6, 0>, &k_onchip<7, 0>, &k_onchip<8, 0>, &k_onchip<9, 0>},
-    {&k_onchip<0, 4>, &k_onchip<1, 4>, &k_onchip<2, 4>, &k_onchip<3, 4>, &k_onchip<4, 4>, &k_onchip<5, 4>,
-     &k_onchip<6, 4>, &k_onchip<7, 4>, &k_onchip<8, 4>, &k_onchip<9, 4>}};
+// [learned][register budget][variant]
+#define LDPC_ONCHIP_ROW(W, N)                                                                                      \
+    {&k_onchip<0, W, N>, &k_onchip<1, W, N>, &k_onchip<2, W, N>, &k_onchip<3, W, N>, &k_onchip<4, W, N>,         \
+     &k_onchip<5, W, N>, &k_onchip<6, W, N>, &k_onchip<7, W, N>, &k_onchip<8, W, N>, &k_onchip<9, W, N>}
+const KernelFn kKernels[2][2][kNumVariants] = {{LDPC_ONCHIP_ROW(0, false), LDPC_ONCHIP_ROW(4, false)},
+                                               {LDPC_ONCHIP_ROW(0, true), LDPC_ONCHIP_ROW(4, true)}};
+#undef LDPC_ONCHIP_ROW
 
 // Threads: whole wavefronts, enough for RPT rows and CPT bits per thread.
 int threads_for(const ldpc_graph &g, const Variant &v) {
@@ -577,7 +582,7 @@ int onchip_num_variants() { return kNumVariants; }
 bool onchip_kernel_spill_free(int variant, int waves_per_simd) {
     if (variant < 0 || variant >= kNumVariants) return false;
     hipFuncAttributes a{};
-    if (hipFuncGetAttributes(&a, (const void *)kKernels[waves_per_simd == 4 ? 1 : 0][variant]) != hipSuccess)
+    if (hipFuncGetAttributes(&a, (const void *)kKernels[0][waves_per_simd == 4 ? 1 : 0][variant]) != hipSuccess)
         return false;
     return a.localSizeBytes == 0;
 }
@@ -595,7 +600,7 @@ int onchip_decode(const ldpc_graph &g, const float *llr, int32_t B, int32_t L, u
     if (!onchip_fits(g)) return LDPC_EUNSUPPORTED;
     if (ws == nullptr || ws_bytes < onchip_workspace_bytes(g, B)) return LDPC_EWORKSPACE;
     const int v = pick(g);
-    const KernelFn fn = kKernels[(g.tuning.set && g.tuning.waves_per_simd == 4) ? 1 : 0][v];
+    const KernelFn fn = kKernels[alpha != nullptr ? 1 : 0][(g.tuning.set && g.tuning.waves_per_simd == 4) ? 1 : 0][v];
     const int threads = threads_for(g, kVariants[v]);
     const size_t lds = lds_of(g, v);
     int grid = 0;
@@ -656,7 +661,7 @@ int onchip_decode_multi(const ldpc_job *jobs, int32_t njobs, int32_t L, uint32_t
                     v = c;
                     break;
                 }
-        const KernelFn fn = kKernels[(g.tuning.set && g.tuning.waves_per_simd == 4) ? 1 : 0][v_own];
+        const KernelFn fn = kKernels[0][(g.tuning.set && g.tuning.waves_per_simd == 4) ? 1 : 0][v_own];
         const int t_own = threads_for(g, kVariants[v_own]);
         const size_t l_own = lds_of(g, v_own);
         bool alone = v == kWideVariant;
