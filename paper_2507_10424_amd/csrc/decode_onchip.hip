@@ -374,6 +374,14 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
         }
 
         fin = __builtin_amdgcn_readfirstlane(fin);
+        // next round's iteration numbers (the bit pass below does not use
+        // them; updated here, they stay out of its divergent branches)
+#pragma unroll
+        for (int q = 0; q < F; ++q) {
+            const bool refilled = (fin >> q) & 1u;
+            tt[q] = refilled ? 1 : tt[q] + 1;
+            ph[q] = (refilled || ph[q] + 1 == early) ? 0 : ph[q] + 1;
+        }
 
         // ---- bit pass -------------------------------------------------------------
 #pragma unroll
@@ -403,12 +411,6 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
                 }
                 lds_st<V>(lds, kEnt * (uint32_t)j, sn);
             }
-        }
-#pragma unroll
-        for (int q = 0; q < F; ++q) {
-            const bool refilled = (fin >> q) & 1u;
-            tt[q] = refilled ? 1 : tt[q] + 1;
-            ph[q] = (refilled || ph[q] + 1 == early) ? 0 : ph[q] + 1;
         }
         __syncthreads();
     }
