@@ -35,7 +35,7 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # 32-bit VALU lane-ops/s: 256 CUs x 64
 # changes the figure no longer applies and `traffic` is reported as null.
 # Summaries: profiles/hbm_bytes_qc64800_regular1024.md.
 MEASURED_TRAFFIC = {
-    ("regular1024", "onchip"): {"bytes": 608489986, "source": "decode_onchip.hip", "sha256_16": "9b25381b6590782a"},
+    ("regular1024", "onchip"): {"bytes": 608518955, "source": "decode_onchip.hip", "sha256_16": "112b8e8d07ecf470"},
     ("qc64800", "check"): {"bytes": 10301304363, "source": "decode_stream.hip", "sha256_16": "e635104923181df8"},
     ("qc64800", "bit"): {"bytes": 5691632051, "source": "decode_stream.hip", "sha256_16": "e635104923181df8"},
 }

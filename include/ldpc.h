@@ -307,7 +307,8 @@ int ldpc_graph_get_tuning(const ldpc_graph *g, ldpc_tuning *t);
  * Autotuner: generates B all-zero frames at ebn0_db on the device, times one
  * warm-up and three decodes (at most max_iter iterations, early exit) for
  * every launch choice that applies to the graph (each fitting on-chip
- * variant, both register budgets, 0..4 workgroups per CU; the streaming path
+ * variant, both register budgets, 0..4 workgroups per CU, leaving out
+ * kernels that spill registers unless nothing else fits; the streaming path
  * with 1, 2, 4, 8 wavefronts per workgroup), times the four fastest again
  * (three interleaved rounds of four decodes), and stores the fastest of those
  * in the graph's tuning record (also returned in *best if non-null).  It synchronises `stream`

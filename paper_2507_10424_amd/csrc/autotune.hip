@@ -114,10 +114,15 @@ extern "C" int ldpc_autotune(ldpc_graph *g, int32_t B, int32_t max_iter, float e
     if (st) return st;
 
     std::vector<ldpc_tuning> cands;
+    // Kernels that spill are never the fastest where a spill-free one fits;
+    // they stay candidates only for graphs that nothing else fits.
+    bool clean_fit = false;
+    for (int v = 0; v < onchip_num_variants(); ++v)
+        clean_fit = clean_fit || (onchip_variant_fits(*g, v) && onchip_kernel_spill_free(v, 0));
     for (int v = 0; v < onchip_num_variants(); ++v) {
         if (!onchip_variant_fits(*g, v)) continue;
         for (int wps : {0, 4}) {
-            if (wps == 4 && !onchip_kernel_spill_free(v, 4)) continue; // the tighter budget spills: never faster
+            if (!onchip_kernel_spill_free(v, wps) && (wps == 4 || clean_fit)) continue;
             for (int wpc : {0, 1, 2, 3, 4}) cands.push_back(ldpc_tuning{1, v, wpc, 4, wps, 0.0f});
         }
     }
