@@ -483,11 +483,15 @@ def bench_multi(args, W, dev, lib):
     from paper_2507_10424_amd import ldpc
     from paper_2507_10424_amd import workloads as wl
     fam, L = W["family"], W["L"]
-    graphs, llrs = [], []
+    graphs, llrs, tunings = [], [], []
     for k, c in enumerate(fam):
         graphs.append(ldpc.build_graph(torch.from_numpy(c["H"]).to(dev)))
         llrs.append(wl.bpsk_awgn_llr_torch(None, W["ebn0"][0], c["rate"], W["seed_noise"] + k, dev, n=c["n"],
                                            batch=c["batch"]))
+        if not args.no_autotune:  # each code's own launch choice, as for one code
+            tunings.append(ldpc.autotune(graphs[-1], min(c["batch"], 65536), L, W["ebn0"][0]))
+    if tunings:
+        log(f"[bench] autotuned variants: {[t['variant'] for t in tunings]}")
     jobs = list(zip(graphs, llrs))
     outs = [ldpc._outputs(c["batch"], c["n"], dev, True) for c in fam]
     ws = torch.empty(int(lib.ldpc_multi_workspace_bytes(len(jobs))), dtype=torch.uint8, device=dev)
@@ -540,7 +544,8 @@ def bench_multi(args, W, dev, lib):
         "value": round(gbits, 3), "unit": "Gbit/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_multi, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
-        "config": {"workload": W["name"], "frames": frames, "max_iter": L, "ebn0_db": W["ebn0"]},
+        "config": {"workload": W["name"], "frames": frames, "max_iter": L, "ebn0_db": W["ebn0"],
+                   "tuning": tunings or None},
         "edge_msg_per_s": 2.0 * edges_iters / (ms_multi * 1e-3), "mean_iters": round(iters / frames, 3),
         "ms_per_step_one_launch_per_code": round(ms_each, 4), "per_code": per_code,
         "small_batches": {"frames": sum(x.shape[0] for x in small_llrs), "ms_one_call": round(ms_small_multi, 4),

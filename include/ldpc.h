@@ -178,8 +178,8 @@ size_t ldpc_multi_workspace_bytes(int32_t njobs);
  * ldpc_minsum_decode for every frame (per-frame early exit; LDPC_NO_EARLY_EXIT
  * and the check period are honoured, the path flags are ignored).  Every graph
  * must fit the on-chip kernel and live on the current device.  Jobs whose
- * batch alone fills the GPU for several rounds of frames run as launches of
- * their own kernels; the others share one persistent launch in which
+ * batch alone fills the GPU run as launches of their own kernels (with the
+ * graph's tuning record); the others share one persistent launch in which
  * workgroups take frames from per-job counters, largest job (frames x edges)
  * first, and move to the next job without waiting for the others.  All
  * launches are enqueued on `stream` in this call.

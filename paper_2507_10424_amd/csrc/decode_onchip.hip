@@ -431,12 +431,15 @@ struct Variant {
 // Exact-degree variants for the regular codes in use first, then masked ones,
 // then four-slot variants of the (3,6) shape (float4 LDS entries: half the
 // LDS instructions and per-frame loop work per frame, twice the LDS per
-// workgroup).  The order is the dispatch order of pick below.
+// workgroup), then bit degree masked at 6 (fewer registers and LDS loads
+// than 8 for codes whose bits have at most 6 checks).  The order is the
+// dispatch order of pick below.
 constexpr Variant kVariants[] = {
     {6, true, 3, true, 2, 4, 2},   {6, true, 8, false, 2, 4, 2},  {9, true, 8, false, 2, 8, 2},
     {12, true, 8, false, 1, 4, 2}, {16, true, 8, false, 1, 8, 2}, {8, false, 8, false, 2, 4, 2},
     {16, false, 16, false, 1, 8, 2}, {6, true, 3, true, 1, 4, 2}, {6, true, 3, true, 2, 4, 4},
-    {6, true, 3, true, 1, 4, 4},
+    {6, true, 3, true, 1, 4, 4},     {6, true, 6, false, 2, 4, 2},  {9, true, 6, false, 2, 8, 2},
+    {12, true, 6, false, 1, 4, 2},   {16, true, 6, false, 1, 8, 2},
 };
 constexpr int kNumVariants = (int)(sizeof(kVariants) / sizeof(kVariants[0]));
 
@@ -470,7 +473,7 @@ struct JobTable {
 // alone would push every variant of the launch into spills.  Jobs that need
 // it get a launch of their own.
 constexpr int kWideVariant = 6;
-static_assert(kNumVariants == 10, "k_onchip_multi dispatches variants 0-5 and 7-9");
+static_assert(kNumVariants == 14, "k_onchip_multi dispatches variants 0-5 and 7-13");
 
 __global__ __launch_bounds__(kMaxThreads) void k_onchip_multi(const JobTable jt, int32_t L, int32_t early) {
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
@@ -485,6 +488,10 @@ __global__ __launch_bounds__(kMaxThreads) void k_onchip_multi(const JobTable jt,
         case 7: run_v<7, false>(jt.job[c], L, early, lds); break;
         case 8: run_v<8, false>(jt.job[c], L, early, lds); break;
         case 9: run_v<9, false>(jt.job[c], L, early, lds); break;
+        case 10: run_v<10, false>(jt.job[c], L, early, lds); break;
+        case 11: run_v<11, false>(jt.job[c], L, early, lds); break;
+        case 12: run_v<12, false>(jt.job[c], L, early, lds); break;
+        case 13: run_v<13, false>(jt.job[c], L, early, lds); break;
         default: break; // the host never places kWideVariant here
         }
         __syncthreads();
@@ -495,7 +502,8 @@ using KernelFn = void (*)(const Job, int32_t, int32_t);
 // [learned][register budget][variant]
 #define LDPC_ONCHIP_ROW(W, N)                                                                                      \
     {&k_onchip<0, W, N>, &k_onchip<1, W, N>, &k_onchip<2, W, N>, &k_onchip<3, W, N>, &k_onchip<4, W, N>,         \
-     &k_onchip<5, W, N>, &k_onchip<6, W, N>, &k_onchip<7, W, N>, &k_onchip<8, W, N>, &k_onchip<9, W, N>}
+     &k_onchip<5, W, N>, &k_onchip<6, W, N>, &k_onchip<7, W, N>, &k_onchip<8, W, N>, &k_onchip<9, W, N>,         \
+     &k_onchip<10, W, N>, &k_onchip<11, W, N>, &k_onchip<12, W, N>, &k_onchip<13, W, N>}
 const KernelFn kKernels[2][2][kNumVariants] = {{LDPC_ONCHIP_ROW(0, false), LDPC_ONCHIP_ROW(4, false)},
                                                {LDPC_ONCHIP_ROW(0, true), LDPC_ONCHIP_ROW(4, true)}};
 #undef LDPC_ONCHIP_ROW
@@ -519,10 +527,15 @@ bool variant_ok(const ldpc_graph &g, int k) {
 
 size_t lds_of(const ldpc_graph &g, int variant) { return lds_bytes_for(g, kVariants[variant].f); }
 
+// Default preference when nothing is tuned: exact degrees first, a column
+// mask of 6 before one of 8, two frame slots before four.
+constexpr int kPickOrder[] = {0, 7, 10, 1, 11, 2, 12, 3, 13, 4, 5, 6, 8, 9};
+static_assert(sizeof(kPickOrder) / sizeof(kPickOrder[0]) == kNumVariants, "every variant has a place");
+
 // The tuned variant if one is set and valid, else the first that fits.
 int pick(const ldpc_graph &g) {
     if (g.tuning.set && variant_ok(g, g.tuning.variant)) return g.tuning.variant;
-    for (int k = 0; k < kNumVariants; ++k)
+    for (int k : kPickOrder)
         if (variant_ok(g, k)) return k;
     return -1;
 }
@@ -629,12 +642,12 @@ int onchip_decode_multi(const ldpc_job *jobs, int32_t njobs, int32_t L, uint32_t
     std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
         return (int64_t)jobs[a].B * jobs[a].g->E > (int64_t)jobs[b].B * jobs[b].g->E;
     });
-    // A job whose batch alone fills every CU for at least kOwnLaunchRounds
-    // rounds of frames gets a launch of its own kernel (its own LDS size,
-    // workgroup size and register budget); so does a job that only the
-    // widest variant fits.  The other jobs share one persistent launch, whose
-    // workgroup size and LDS are the maxima over them.
-    constexpr int64_t kOwnLaunchRounds = 4;
+    // A job whose batch alone fills every CU at least once gets a launch of
+    // its own kernel (its own LDS size, workgroup size, register budget and
+    // tuned workgroups per CU); so does a job that only the widest variant
+    // fits.  The other jobs share one persistent launch, whose workgroup size
+    // and LDS are the maxima over them.
+    constexpr int64_t kOwnLaunchRounds = 1;
     JobTable jt{};
     int threads = 64;
     size_t lds = 0;
@@ -647,6 +660,7 @@ int onchip_decode_multi(const ldpc_job *jobs, int32_t njobs, int32_t L, uint32_t
         int threads;
         size_t lds;
         int num_cu;
+        int wg_per_cu; // tuned cap, 0 for none
     };
     std::vector<Own> own;
     int32_t nj = 0;
@@ -679,7 +693,7 @@ int onchip_decode_multi(const ldpc_job *jobs, int32_t njobs, int32_t L, uint32_t
         if (alone) {
             own.push_back(Own{make_job(g, v_own, jb.llr_dev, jb.B, jb.bits_dev, jb.post_dev, jb.iters_dev, jb.ok_dev,
                                        nullptr, nullptr, queues + k),
-                              fn, t_own, l_own, g.num_cu});
+                              fn, t_own, l_own, g.num_cu, g.tuning.set ? g.tuning.wg_per_cu : 0});
             continue;
         }
         const int t = threads_for(g, kVariants[v]);
@@ -696,7 +710,7 @@ int onchip_decode_multi(const ldpc_job *jobs, int32_t njobs, int32_t L, uint32_t
     k_zero_words<<<1, 64, 0, stream>>>(queues, njobs);
     for (const Own &o : own) {
         int grid = 0;
-        const int st = launch_grid((const void *)o.fn, o.threads, o.lds, o.num_cu, o.J.B, 0, &grid,
+        const int st = launch_grid((const void *)o.fn, o.threads, o.lds, o.num_cu, o.J.B, o.wg_per_cu, &grid,
                                    kVariants[o.J.variant].f);
         if (st) return st;
         const Job J = o.J;

@@ -28,7 +28,7 @@ def test_all_launch_choices_agree(tdev):
     llr = torch.from_numpy(llr_np).to(dev)
     ref = oracle_decode(H, llr_np, 40)
     tried = 0
-    for v, wpc, wps in itertools.product(range(10), (0, 1, 3), (0, 4)):
+    for v, wpc, wps in itertools.product(range(14), (0, 1, 3), (0, 4)):
         try:
             ldpc.set_tuning(g, 1, variant=v, wg_per_cu=wpc, waves_per_simd=wps)
         except ldpc.LdpcError as e:
