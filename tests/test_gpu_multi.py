@@ -111,3 +111,23 @@ def test_multi_big_job_runs_alone(tdev):
         sel = slice(0, min(llr.shape[0], 3000))
         got = tuple(t[sel].cpu().numpy() for t in o)
         assert_parity(got, oracle_decode(H, llr[sel], 30), f"big/small {k}")
+
+
+def test_multi_check_period_and_no_early_exit(tdev):
+    """The multi-code call honours the codeword-test period and
+    LDPC_NO_EARLY_EXIT like the single-code decode."""
+    torch, dev = tdev
+    from paper_2507_10424_amd import ldpc
+    fam = wl.qc_multi_code_family(seed=7)[:3]
+    jobs, inputs = [], []
+    for k, c in enumerate(fam):
+        B = 150 + 50 * k
+        llr = wl.bpsk_awgn_llr(None, 2.0, c["rate"], seed=800 + k, n=c["n"], batch=B)
+        g = ldpc.build_graph(torch.from_numpy(c["H"]).to(dev))
+        jobs.append((g, torch.from_numpy(llr).to(dev)))
+        inputs.append((c["H"], llr))
+    for flags in (ldpc.check_period(6), ldpc.LDPC_NO_EARLY_EXIT):
+        outs = ldpc.minsum_decode_multi(jobs, 30, flags=flags)
+        torch.cuda.synchronize()
+        for k, ((H, llr), o) in enumerate(zip(inputs, outs)):
+            assert_parity(tuple(t.cpu().numpy() for t in o), oracle_decode(H, llr, 30, flags), f"multi flags {flags} {k}")
