@@ -102,7 +102,7 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true", help="skip the autotuner (library defaults)")
     ap.add_argument("--tuning", default=None,
                     help="set the tuning record instead of autotuning: path,variant,wg_per_cu,stream_waves,"
-                         "waves_per_simd (as printed by a tuned run)")
+                         "waves_per_simd[,stream_nt] (as printed by a tuned run)")
     ap.add_argument("--path", default="auto", choices=["auto", "stream", "onchip"])
     ap.add_argument("--check-period", type=int, default=1,
                     help="codeword test after every k-th iteration (the paper's GPU runs use 6)")
@@ -194,8 +194,8 @@ def main():
 
     tuning = None
     if args.tuning:
-        p_, v_, w_, sw_, ws_ = (int(t) for t in args.tuning.split(","))
-        ldpc.set_tuning(g, p_, v_, w_, sw_, ws_)
+        vals = [int(t) for t in args.tuning.split(",")]
+        ldpc.set_tuning(g, *vals)
         tuning = ldpc.get_tuning(g)
         log(f"[bench] tuning set: {tuning}")
     elif not args.no_autotune and args.path == "auto":

@@ -286,6 +286,10 @@ int ldpc_adam_step(float *param_dev, const float *grad_dev, float *m1_dev, float
  *   waves_per_simd  on-chip register budget: 0 the compiler's, 4 at least four
  *                 resident waves per SIMD (fewer registers per thread)
  *   ms            ldpc_autotune: mean time of one decode of the tuning batch
+ *   stream_nt     streaming path: 1 marks the message loads and stores
+ *                 non-temporal (they stream through the caches and leave them
+ *                 to the posterior gathers), 0 not, -1 by size (non-temporal
+ *                 when one iteration's messages exceed 2 GiB)
  * LDPC_FORCE_STREAM / LDPC_FORCE_ONCHIP still override the path.
  */
 typedef struct ldpc_tuning {
@@ -295,6 +299,7 @@ typedef struct ldpc_tuning {
     int32_t stream_waves;
     int32_t waves_per_simd;
     float ms;
+    int32_t stream_nt;
 } ldpc_tuning;
 
 /* Set (t != NULL) or clear (t == NULL) the tuning record.  Not thread-safe

@@ -25,6 +25,8 @@
 // The first check launch computes the syndrome of the channel decision, so a
 // frame whose channel decision is a codeword stops with 0 iterations (the
 // pre-loop test of the paper's kernel listing).
+#include <type_traits>
+
 #include "ldpc_internal.h"
 
 namespace ldpc {
@@ -74,6 +76,18 @@ StreamWs carve(const ldpc_graph &g, int32_t B, void *base, size_t *total) {
     return w;
 }
 
+// Message (eta) accesses, optionally non-temporal: one iteration's messages
+// stream through the caches once, and marked so they leave the L2 to the
+// posterior gathers of the check kernel.
+template <bool NT> __device__ __forceinline__ float ld_msg(const float *p) {
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <bool NT> __device__ __forceinline__ void st_msg(float *p, float v) {
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
 __global__ void k_flags_init(int32_t B, int32_t frames, uint32_t *done, uint32_t *u0, uint32_t *u1, int32_t *conv) {
     const int32_t f = blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= frames) return;
@@ -107,6 +121,7 @@ __global__ __launch_bounds__(256) void k_to_tiles(const float *__restrict__ llr,
 
 // One wavefront = one check row x one frame tile.  `t` is the iteration
 // being computed (1-based).
+template <bool NT>
 __global__ __launch_bounds__(512) void k_check(const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx,
                                                const int32_t *__restrict__ row_class, int32_t m, int32_t n, int64_t E,
                                                int32_t B, int32_t row_blocks, const float *__restrict__ r,
@@ -133,7 +148,7 @@ __global__ __launch_bounds__(512) void k_check(const int32_t *__restrict__ row_p
     for (int32_t e = e0; e < e1; ++e) {
         const float sj = sv[(size_t)col_idx[e] * kTile];
         syn ^= sj < 0.0f;
-        const float x = (t == 1) ? sj : sj - et[(size_t)e * kTile];
+        const float x = (t == 1) ? sj : sj - ld_msg<NT>(&et[(size_t)e * kTile]);
         const float a = fabsf(x);
         const uint32_t ng = x < 0.0f;
         par ^= ng;
@@ -161,11 +176,11 @@ __global__ __launch_bounds__(512) void k_check(const int32_t *__restrict__ row_p
             ng = (negs >> k) & 1u;
         } else { // rows longer than 32: recompute the sign of x (inputs unchanged so far)
             const float sj = sv[(size_t)col_idx[e] * kTile];
-            const float x = (t == 1) ? sj : sj - et[(size_t)e * kTile];
+            const float x = (t == 1) ? sj : sj - ld_msg<NT>(&et[(size_t)e * kTile]);
             ng = x < 0.0f;
         }
         const float mag = (k == am) ? min1 : min0;
-        if (act) et[(size_t)e * kTile] = (par ^ ng) ? -mag : mag;
+        if (act) st_msg<NT>(&et[(size_t)e * kTile], (par ^ ng) ? -mag : mag);
     }
     if (act && syn) unsat[f] = 1u;
 }
@@ -174,7 +189,7 @@ __global__ __launch_bounds__(512) void k_check(const int32_t *__restrict__ row_p
 // per wavefront: the loops are unrolled and every load of the wavefront's
 // rows is issued before any use, so it keeps 2 DC RPW requests in flight,
 // and there are RPW times fewer wavefronts to launch.
-template <int DC, int RPW>
+template <int DC, int RPW, bool NT>
 __global__ __launch_bounds__(512) void k_check_dc(const int32_t *__restrict__ col_idx,
                                                   const int32_t *__restrict__ row_class, int32_t m, int32_t n,
                                                   int64_t E, int32_t row_blocks, const float *__restrict__ r,
@@ -201,7 +216,7 @@ __global__ __launch_bounds__(512) void k_check_dc(const int32_t *__restrict__ co
 #pragma unroll
         for (int k = 0; k < DC; ++k) sj[q][k] = sv[(size_t)col_idx[e0 + k] * kTile];
 #pragma unroll
-        for (int k = 0; k < DC; ++k) ev[q][k] = (t == 1) ? 0.0f : et[(size_t)(e0 + k) * kTile];
+        for (int k = 0; k < DC; ++k) ev[q][k] = (t == 1) ? 0.0f : ld_msg<NT>(&et[(size_t)(e0 + k) * kTile]);
     }
     uint32_t syn = 0;
 #pragma unroll
@@ -238,7 +253,7 @@ __global__ __launch_bounds__(512) void k_check_dc(const int32_t *__restrict__ co
 #pragma unroll
             for (int k = 0; k < DC; ++k) {
                 const float mag = (k == am) ? min1 : min0;
-                et[(size_t)(e0 + k) * kTile] = (par ^ (x[k] < 0.0f ? 1u : 0u)) ? -mag : mag;
+                st_msg<NT>(&et[(size_t)(e0 + k) * kTile], (par ^ (x[k] < 0.0f ? 1u : 0u)) ? -mag : mag);
             }
         }
     }
@@ -250,7 +265,7 @@ __global__ __launch_bounds__(512) void k_check_dc(const int32_t *__restrict__ co
 // message loads) before any add, so a wavefront keeps up to 9 CPW requests in
 // flight; longer columns continue in groups of 8.  The adds of a column run
 // in ascending check order from +0, then r is added.
-template <int CPW>
+template <int CPW, bool NT>
 __global__ __launch_bounds__(512) void k_bit(const int32_t *__restrict__ col_ptr, const int32_t *__restrict__ csc_edge,
                                              int32_t n, int64_t E, int32_t col_blocks, const float *__restrict__ r,
                                              float *__restrict__ s, const float *__restrict__ eta,
@@ -295,7 +310,7 @@ __global__ __launch_bounds__(512) void k_bit(const int32_t *__restrict__ col_ptr
         const bool any = k1[c] > k0[c];
 #pragma unroll
         for (int u = 0; u < 8; ++u)
-            ev[c][u] = any ? et[(size_t)(k0[c] + u < k1[c] ? idx[u] : idx[0]) * kTile] : 0.0f;
+            ev[c][u] = any ? ld_msg<NT>(&et[(size_t)(k0[c] + u < k1[c] ? idx[u] : idx[0]) * kTile]) : 0.0f;
     }
 #pragma unroll
     for (int c = 0; c < CPW; ++c) {
@@ -308,7 +323,7 @@ __global__ __launch_bounds__(512) void k_bit(const int32_t *__restrict__ col_ptr
 #pragma unroll
             for (int u = 0; u < 8; ++u) idx[u] = csc_edge[k + u];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) e2[u] = et[(size_t)(k + u < k1[c] ? idx[u] : idx[0]) * kTile];
+            for (int u = 0; u < 8; ++u) e2[u] = ld_msg<NT>(&et[(size_t)(k + u < k1[c] ? idx[u] : idx[0]) * kTile]);
 #pragma unroll
             for (int u = 0; u < 8; ++u) acc[c] = (k + u < k1[c]) ? acc[c] + e2[u] : acc[c];
         }
@@ -407,30 +422,44 @@ int stream_decode(const ldpc_graph &g, const float *llr, int32_t B, int32_t L, u
     // unrolled check kernel when every row has 6 or 7 edges
     const int32_t regular = (g.dc_min == g.dc_max && (g.dc_max == 6 || g.dc_max == 7)) ? g.dc_max : 0;
 
+    // Non-temporal message accesses: the tuning record's choice, else when one
+    // iteration's messages (4 E bytes per frame) exceed 2 GiB and so cannot
+    // stay in the caches between the two kernels anyway.
+    const bool nt_msgs = (g.tuning.set && g.tuning.path == 2 && g.tuning.stream_nt >= 0)
+                             ? g.tuning.stream_nt == 1
+                             : (double)nt * kTile * 4.0 * (double)g.E > 2.0 * 1024 * 1024 * 1024;
+
     k_flags_init<<<(frames + 255) / 256, 256, 0, stream>>>(B, frames, w.done, w.unsat[0], w.unsat[1], w.conv);
     k_to_tiles<<<nt * nchunks, 256, 0, stream>>>(llr, B, g.n, w.r);
-    for (int32_t t = 1; t <= L; ++t) {
-        timed_launch(K_CHECK, stream, [&] {
-            if (regular == 6)
-                k_check_dc<6, kRowsPerWave><<<nt * row_blocks_dc, 64 * waves, 0, stream>>>(
-                    g.col_idx, g.row_class, g.m, g.n, g.E, row_blocks_dc, w.r, w.s, w.eta, w.done, w.unsat[t & 1], t,
-                    alpha, beta, ncls);
-            else if (regular == 7)
-                k_check_dc<7, kRowsPerWave><<<nt * row_blocks_dc, 64 * waves, 0, stream>>>(
-                    g.col_idx, g.row_class, g.m, g.n, g.E, row_blocks_dc, w.r, w.s, w.eta, w.done, w.unsat[t & 1], t,
-                    alpha, beta, ncls);
-            else
-                k_check<<<nt * row_blocks, 64 * waves, 0, stream>>>(g.row_ptr, g.col_idx, g.row_class, g.m, g.n,
-                                                                    g.E, B, row_blocks, w.r, w.s, w.eta, w.done,
-                                                                    w.unsat[t & 1], t, alpha, beta, ncls);
-        });
-        timed_launch(K_BIT, stream, [&] {
-            k_bit<kColsPerWave><<<nt * col_blocks, 64 * waves, 0, stream>>>(
-                g.col_ptr, g.csc_edge, g.n, g.E, col_blocks, w.r, w.s, w.eta, w.done, w.unsat[t & 1],
-                w.unsat[(t + 1) & 1], w.conv, t,
-                (period > 0 && (t - 1) % period == 0) ? 1 : 0); // is the decision of iteration t - 1 tested?
-        });
-    }
+    auto iterate = [&](auto nt_tag) {
+        constexpr bool NT = decltype(nt_tag)::value;
+        for (int32_t t = 1; t <= L; ++t) {
+            timed_launch(K_CHECK, stream, [&] {
+                if (regular == 6)
+                    k_check_dc<6, kRowsPerWave, NT><<<nt * row_blocks_dc, 64 * waves, 0, stream>>>(
+                        g.col_idx, g.row_class, g.m, g.n, g.E, row_blocks_dc, w.r, w.s, w.eta, w.done, w.unsat[t & 1],
+                        t, alpha, beta, ncls);
+                else if (regular == 7)
+                    k_check_dc<7, kRowsPerWave, NT><<<nt * row_blocks_dc, 64 * waves, 0, stream>>>(
+                        g.col_idx, g.row_class, g.m, g.n, g.E, row_blocks_dc, w.r, w.s, w.eta, w.done, w.unsat[t & 1],
+                        t, alpha, beta, ncls);
+                else
+                    k_check<NT><<<nt * row_blocks, 64 * waves, 0, stream>>>(
+                        g.row_ptr, g.col_idx, g.row_class, g.m, g.n, g.E, B, row_blocks, w.r, w.s, w.eta, w.done,
+                        w.unsat[t & 1], t, alpha, beta, ncls);
+            });
+            timed_launch(K_BIT, stream, [&] {
+                k_bit<kColsPerWave, NT><<<nt * col_blocks, 64 * waves, 0, stream>>>(
+                    g.col_ptr, g.csc_edge, g.n, g.E, col_blocks, w.r, w.s, w.eta, w.done, w.unsat[t & 1],
+                    w.unsat[(t + 1) & 1], w.conv, t,
+                    (period > 0 && (t - 1) % period == 0) ? 1 : 0); // is the decision of iteration t - 1 tested?
+            });
+        }
+    };
+    if (nt_msgs)
+        iterate(std::true_type{});
+    else
+        iterate(std::false_type{});
     uint32_t *unsat_final = w.unsat[(L + 1) & 1];
     k_syndrome<<<nt * row_blocks, 64 * waves, 0, stream>>>(g.row_ptr, g.col_idx, g.m, g.n, row_blocks, L == 0 ? w.r : w.s,
                                                     w.done, unsat_final);

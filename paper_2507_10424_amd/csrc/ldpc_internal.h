@@ -41,6 +41,7 @@ struct ldpc_graph {
         int wg_per_cu = 0;    // on-chip workgroups per CU (0: occupancy limit)
         int waves_per_simd = 0; // on-chip register budget: 0 compiler's, 4 at least 4 waves per SIMD
         int stream_waves = 4; // wavefronts per workgroup of the streaming kernels
+        int stream_nt = -1;   // non-temporal message accesses: 1 yes, 0 no, -1 by size
     } tuning;
 };
 

@@ -38,11 +38,11 @@ def test_all_launch_choices_agree(tdev):
         torch.cuda.synchronize()
         assert_parity(tuple(t.cpu().numpy() for t in out), ref, f"variant {v} wpc {wpc} wps {wps}")
         tried += 1
-    for waves in (1, 2, 4, 8):
-        ldpc.set_tuning(g, 2, stream_waves=waves)
+    for waves, nt in itertools.product((1, 2, 4, 8), (0, 1)):
+        ldpc.set_tuning(g, 2, stream_waves=waves, stream_nt=nt)
         out = ldpc.minsum_decode(g, llr, 40)
         torch.cuda.synchronize()
-        assert_parity(tuple(t.cpu().numpy() for t in out), ref, f"stream waves {waves}")
+        assert_parity(tuple(t.cpu().numpy() for t in out), ref, f"stream waves {waves} non-temporal {nt}")
     assert tried >= 4 * 3 * 2
     ldpc.set_tuning(g, None)
     assert ldpc.get_tuning(g)["path"] == 0
