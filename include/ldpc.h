@@ -275,12 +275,13 @@ int ldpc_adam_step(float *param_dev, const float *grad_dev, float *m1_dev, float
 
 /*
  * Launch choices of a graph ("tuning record").  Without one, decoding takes
- * the on-chip path whenever the graph fits (its first fitting kernel
- * variant, as many workgroups as fit on each CU) and otherwise the streaming
- * path with 4 wavefronts per workgroup.
+ * the on-chip path whenever the graph fits (the preferred fitting kernel
+ * variant: exact degrees, then the tightest degree masks, two frame slots;
+ * as many workgroups as fit on each CU) and otherwise the streaming path with
+ * 4 wavefronts per workgroup.
  *   path          1 on-chip, 2 streaming (0 in ldpc_graph_get_tuning: none set)
- *   variant       on-chip kernel variant (degree template and rows per
- *                 thread), -1 for the first that fits
+ *   variant       on-chip kernel variant (degree templates, rows and bits
+ *                 per thread, frame slots), -1 for the preferred one
  *   wg_per_cu     on-chip workgroups per CU, 0 for the occupancy limit
  *   stream_waves  wavefronts per workgroup of the streaming kernels (1..8)
  *   waves_per_simd  on-chip register budget: 0 the compiler's, 4 at least four
@@ -314,10 +315,11 @@ int ldpc_graph_get_tuning(const ldpc_graph *g, ldpc_tuning *t);
  * every launch choice that applies to the graph (each fitting on-chip
  * variant, both register budgets, 0..4 workgroups per CU, leaving out
  * kernels that spill registers unless nothing else fits; the streaming path
- * with 1, 2, 4, 8 wavefronts per workgroup), times the four fastest again
- * (three interleaved rounds of four decodes), and stores the fastest of those
- * in the graph's tuning record (also returned in *best if non-null).  It synchronises `stream`
- * and creates two HIP events; do not capture it.  The workspace needs
+ * with 1, 2, 4, 8 wavefronts per workgroup, with and without non-temporal
+ * message accesses), times the four fastest again (three interleaved rounds
+ * of four decodes), and stores the fastest of those in the graph's tuning
+ * record (also returned in *best if non-null).  It synchronises `stream` and
+ * creates two HIP events; do not capture it.  The workspace needs
  * ldpc_autotune_workspace_bytes(g, B) bytes.
  * Errors: LDPC_EINVAL, LDPC_EWORKSPACE, LDPC_EHIP.
  */
