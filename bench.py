@@ -114,7 +114,7 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true", help="skip the autotuner (library defaults)")
     ap.add_argument("--tuning", default=None,
                     help="set the tuning record instead of autotuning: path,variant,wg_per_cu,stream_waves,"
-                         "waves_per_simd[,stream_nt] (as printed by a tuned run)")
+                         "waves_per_simd[,stream_nt[,stream_chunk]] (as printed by a tuned run)")
     ap.add_argument("--path", default="auto", choices=["auto", "stream", "onchip"])
     ap.add_argument("--check-period", type=int, default=1,
                     help="codeword test after every k-th iteration (the paper's GPU runs use 6)")
@@ -342,12 +342,15 @@ def main():
 
         sstep()
         torch.cuda.synchronize()
-        lib.ldpc_timing_enable(1)
         ev0.record()
         sstep()
         ev1.record()
         torch.cuda.synchronize()
         sms = ev0.elapsed_time(ev1)
+        # kernel durations from one more step with per-dispatch timing
+        lib.ldpc_timing_enable(1)
+        sstep()
+        torch.cuda.synchronize()
         st_k = {}
         for kid, kname in [(0, "check"), (1, "bit")]:
             ms_k, cnt = ctypes.c_double(), ctypes.c_int64()

@@ -290,7 +290,13 @@ int ldpc_adam_step(float *param_dev, const float *grad_dev, float *m1_dev, float
  *   stream_nt     streaming path: 1 marks the message loads and stores
  *                 non-temporal (they stream through the caches and leave them
  *                 to the posterior gathers), 0 not, -1 by size (non-temporal
- *                 when one iteration's messages exceed 2 GiB)
+ *                 when one iteration's messages of a chunk exceed 2 GiB)
+ *   stream_chunk  streaming path: tiles of 64 frames decoded together, all
+ *                 iterations of one chunk before the next, so that a chunk's
+ *                 state can stay in the last-level (Infinity) cache between
+ *                 the launches; 0 all tiles at once, k > 0 k tiles, -1 by size
+ *                 (as many tiles as fit 200 MiB of posteriors, channel LLRs
+ *                 and messages, at least one)
  * LDPC_FORCE_STREAM / LDPC_FORCE_ONCHIP still override the path.
  */
 typedef struct ldpc_tuning {
@@ -301,6 +307,7 @@ typedef struct ldpc_tuning {
     int32_t waves_per_simd;
     float ms;
     int32_t stream_nt;
+    int32_t stream_chunk;
 } ldpc_tuning;
 
 /* Set (t != NULL) or clear (t == NULL) the tuning record.  Not thread-safe
@@ -316,7 +323,7 @@ int ldpc_graph_get_tuning(const ldpc_graph *g, ldpc_tuning *t);
  * variant, both register budgets, 0..4 workgroups per CU, leaving out
  * kernels that spill registers unless nothing else fits; the streaming path
  * with 1, 2, 4, 8 wavefronts per workgroup, with and without non-temporal
- * message accesses), times the four fastest again (three interleaved rounds
+ * message accesses, whole batch and chunks by size where those differ), times the four fastest again (three interleaved rounds
  * of four decodes), and stores the fastest of those in the graph's tuning
  * record (also returned in *best if non-null).  It synchronises `stream` and
  * creates two HIP events; do not capture it.  The workspace needs

@@ -72,6 +72,7 @@ extern "C" int ldpc_graph_set_tuning(ldpc_graph *g, const ldpc_tuning *t) {
     if (t->path == 1 && t->variant < 0 && !onchip_fits(*g)) return LDPC_EUNSUPPORTED;
     if (t->path == 2 && (t->stream_waves < 1 || t->stream_waves > 8)) return LDPC_EINVAL;
     if (t->stream_nt < -1 || t->stream_nt > 1) return LDPC_EINVAL;
+    if (t->stream_chunk < -1) return LDPC_EINVAL;
     if (t->path == 1 && t->waves_per_simd != 0 && t->waves_per_simd != 4) return LDPC_EINVAL;
     g->tuning.set = true;
     g->tuning.path = t->path;
@@ -80,6 +81,7 @@ extern "C" int ldpc_graph_set_tuning(ldpc_graph *g, const ldpc_tuning *t) {
     g->tuning.waves_per_simd = t->path == 1 ? t->waves_per_simd : 0;
     g->tuning.stream_waves = t->path == 2 ? t->stream_waves : 4;
     g->tuning.stream_nt = t->path == 2 ? t->stream_nt : -1;
+    g->tuning.stream_chunk = t->path == 2 ? t->stream_chunk : -1;
     return LDPC_OK;
 }
 
@@ -90,6 +92,7 @@ extern "C" int ldpc_graph_get_tuning(const ldpc_graph *g, ldpc_tuning *t) {
     t->wg_per_cu = g->tuning.wg_per_cu;
     t->stream_waves = g->tuning.stream_waves;
     t->stream_nt = g->tuning.stream_nt;
+    t->stream_chunk = g->tuning.stream_chunk;
     t->waves_per_simd = g->tuning.waves_per_simd;
     t->ms = 0.0f;
     return LDPC_OK;
@@ -126,11 +129,16 @@ extern "C" int ldpc_autotune(ldpc_graph *g, int32_t B, int32_t max_iter, float e
         if (!onchip_variant_fits(*g, v)) continue;
         for (int wps : {0, 4}) {
             if (!onchip_kernel_spill_free(v, wps) && (wps == 4 || clean_fit)) continue;
-            for (int wpc : {0, 1, 2, 3, 4}) cands.push_back(ldpc_tuning{1, v, wpc, 4, wps, 0.0f, -1});
+            for (int wpc : {0, 1, 2, 3, 4}) cands.push_back(ldpc_tuning{1, v, wpc, 4, wps, 0.0f, -1, -1});
         }
     }
-    for (int nt : {0, 1})
-        for (int waves : {1, 2, 4, 8}) cands.push_back(ldpc_tuning{2, -1, 0, waves, 0, 0.0f, nt});
+    // Chunked streaming only where the size rule splits this batch.
+    const bool chunks = stream_chunk_tiles(*g, B, -1) < stream_chunk_tiles(*g, B, 0);
+    for (int chunk : {0, -1}) {
+        if (chunk == -1 && !chunks) continue;
+        for (int nt : {0, 1})
+            for (int waves : {1, 2, 4, 8}) cands.push_back(ldpc_tuning{2, -1, 0, waves, 0, 0.0f, nt, chunk});
+    }
 
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return LDPC_EHIP;

@@ -626,7 +626,7 @@ int onchip_decode(const ldpc_graph &g, const float *llr, int32_t B, int32_t L, u
     const int32_t early = test_period(flags);
     const Job J = make_job(g, v, llr, B, bits, post, iters, ok, alpha, beta, queue);
     k_zero_words<<<1, 64, 0, stream>>>(queue, 1);
-    timed_launch(K_ONCHIP, stream, [&] { fn<<<grid, threads, lds, stream>>>(J, L, early); });
+    timed_launch(K_ONCHIP, fn, grid, threads, lds, stream, J, L, early);
     return hipGetLastError() == hipSuccess ? LDPC_OK : LDPC_EHIP;
 }
 
@@ -717,13 +717,13 @@ int onchip_decode_multi(const ldpc_job *jobs, int32_t njobs, int32_t L, uint32_t
         const KernelFn fn = o.fn;
         const int t = o.threads;
         const size_t l = o.lds;
-        timed_launch(K_ONCHIP, stream, [&] { fn<<<grid, t, l, stream>>>(J, L, early); });
+        timed_launch(K_ONCHIP, fn, grid, t, l, stream, J, L, early);
     }
     if (frames > 0) {
         int grid = 0;
         const int st = launch_grid((const void *)k_onchip_multi, threads, lds, num_cu, frames, 0, &grid);
         if (st) return st;
-        timed_launch(K_ONCHIP, stream, [&] { k_onchip_multi<<<grid, threads, lds, stream>>>(jt, L, early); });
+        timed_launch(K_ONCHIP, k_onchip_multi, grid, threads, lds, stream, jt, L, early);
     }
     return hipGetLastError() == hipSuccess ? LDPC_OK : LDPC_EHIP;
 }

@@ -124,7 +124,7 @@ __global__ __launch_bounds__(256) void k_to_tiles(const float *__restrict__ llr,
 template <bool NT>
 __global__ __launch_bounds__(512) void k_check(const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx,
                                                const int32_t *__restrict__ row_class, int32_t m, int32_t n, int64_t E,
-                                               int32_t B, int32_t row_blocks, const float *__restrict__ r,
+                                               int32_t row_blocks, const float *__restrict__ r,
                                                const float *__restrict__ s, float *__restrict__ eta,
                                                const uint32_t *__restrict__ done, uint32_t *__restrict__ unsat,
                                                int32_t t, const float *__restrict__ alpha,
@@ -202,19 +202,38 @@ __global__ __launch_bounds__(512) void k_check_dc(const int32_t *__restrict__ co
     const int32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int32_t row0 = ((bid % row_blocks) * (int32_t)(blockDim.x >> 6) + w) * RPW;
     const int lane = threadIdx.x & 63;
+    if (row0 >= m) return;
     const int32_t f = tile * kTile + lane;
-    const bool act = !done[f];
-    if (row0 >= m || !__any(act)) return;
+    const uint32_t dn = done[f];
+    // The rows' column indices (scalar loads) are requested before the frame
+    // flags are tested, so that their latencies overlap; the empty asm, which
+    // takes a value that depends on every index, keeps the compiler from
+    // moving the index loads behind the test.
+    int32_t ci[RPW][DC];
+    int32_t all = 0;
+#pragma unroll
+    for (int q = 0; q < RPW; ++q) {
+        // rows of equal degree: CSR offsets are row * DC; a row past m repeats row0
+        const int64_t e0 = (int64_t)(row0 + q < m ? row0 + q : row0) * DC;
+#pragma unroll
+        for (int k = 0; k < DC; ++k) ci[q][k] = col_idx[e0 + k];
+    }
+#pragma unroll
+    for (int q = 0; q < RPW; ++q)
+#pragma unroll
+        for (int k = 0; k < DC; ++k) all ^= ci[q][k];
+    asm volatile("" ::"s"(all));
+    const bool act = dn == 0u;
+    if (!__any(act)) return;
 
     const float *sv = (t == 1 ? r : s) + (size_t)tile * n * kTile + lane;
     float *et = eta + (size_t)tile * E * kTile + lane;
     float sj[RPW][DC], ev[RPW][DC];
 #pragma unroll
     for (int q = 0; q < RPW; ++q) {
-        // rows of equal degree: CSR offsets are row * DC; a row past m repeats row0
         const int64_t e0 = (int64_t)(row0 + q < m ? row0 + q : row0) * DC;
 #pragma unroll
-        for (int k = 0; k < DC; ++k) sj[q][k] = sv[(size_t)col_idx[e0 + k] * kTile];
+        for (int k = 0; k < DC; ++k) sj[q][k] = sv[(size_t)ci[q][k] * kTile];
 #pragma unroll
         for (int k = 0; k < DC; ++k) ev[q][k] = (t == 1) ? 0.0f : ld_msg<NT>(&et[(size_t)(e0 + k) * kTile]);
     }
@@ -276,12 +295,42 @@ __global__ __launch_bounds__(512) void k_bit(const int32_t *__restrict__ col_ptr
     const int32_t tile = bid / col_blocks;
     const int32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int32_t cb = bid % col_blocks;
+    static_assert(CPW <= 8, "col_ptr has 8 entries of padding");
     const int32_t col0 = (cb * (int32_t)(blockDim.x >> 6) + w) * CPW;
     const int lane = threadIdx.x & 63;
+    if (col0 >= n) return;
     const int32_t f = tile * kTile + lane;
-    bool act = !done[f];
-    if (col0 >= n || !__any(act)) return;
-    const bool stop = act && test_now && unsat_cur[f] == 0u;
+    const uint32_t dn = done[f], uc = unsat_cur[f];
+    // Column pointers and the first 8 CSC entries of each column (scalar
+    // loads) are requested before the frame flags are tested, so that their
+    // latencies overlap; the empty asm, which takes a value that depends on
+    // every index and the test flag, keeps the compiler from moving those
+    // loads behind the test.
+    // col_ptr at col0 .. col0 + CPW (in bounds: 8 entries of padding equal to
+    // E, so that columns past n get k0 = k1 = E, no messages)
+    int32_t kp[CPW + 1], k0[CPW], k1[CPW], idx0[CPW][8];
+#pragma unroll
+    for (int c = 0; c <= CPW; ++c) kp[c] = col_ptr[col0 + c];
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+        k0[c] = kp[c];
+        k1[c] = kp[c + 1];
+    }
+#pragma unroll
+    for (int c = 0; c < CPW; ++c)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) idx0[c][u] = csc_edge[k0[c] + u]; // in bounds: 8 entries of padding
+    int32_t all = 0;
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+        all ^= k1[c];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) all ^= idx0[c][u];
+    }
+    asm volatile("" ::"s"(all), "v"(uc));
+    bool act = dn == 0u;
+    if (!__any(act)) return;
+    const bool stop = act && test_now && uc == 0u;
     if (col0 == 0) { // the wavefront of column 0 keeps the per-frame flags
         if (stop) {
             done[f] = 1u;
@@ -293,24 +342,18 @@ __global__ __launch_bounds__(512) void k_bit(const int32_t *__restrict__ col_ptr
     act = act && !stop;
     if (!__any(act)) return;
     const float *et = eta + (size_t)tile * E * kTile + lane;
-    int32_t k0[CPW], k1[CPW];
     float rv[CPW], acc[CPW], ev[CPW][8];
 #pragma unroll
     for (int c = 0; c < CPW; ++c) {
         const int32_t col = col0 + c < n ? col0 + c : col0;
-        k0[c] = col_ptr[col];
-        k1[c] = col0 + c < n ? col_ptr[col + 1] : k0[c]; // columns past n: no messages
         rv[c] = r[((size_t)tile * n + col) * kTile + lane];
     }
 #pragma unroll
     for (int c = 0; c < CPW; ++c) {
-        int32_t idx[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) idx[u] = csc_edge[k0[c] + u]; // in bounds: 8 entries of padding
         const bool any = k1[c] > k0[c];
 #pragma unroll
         for (int u = 0; u < 8; ++u)
-            ev[c][u] = any ? ld_msg<NT>(&et[(size_t)(k0[c] + u < k1[c] ? idx[u] : idx[0]) * kTile]) : 0.0f;
+            ev[c][u] = any ? ld_msg<NT>(&et[(size_t)(k0[c] + u < k1[c] ? idx0[c][u] : idx0[c][0]) * kTile]) : 0.0f;
     }
 #pragma unroll
     for (int c = 0; c < CPW; ++c) {
@@ -396,6 +439,20 @@ __global__ __launch_bounds__(256) void k_from_tiles(const float *__restrict__ r,
 
 } // namespace
 
+// Chunk budget of the size rule: a chunk's r, s and messages (4 (2n + E)
+// bytes per frame) take at most this much of the 256 MiB Infinity Cache.
+constexpr double kChunkBytes = 200.0 * 1024 * 1024;
+
+int32_t stream_chunk_tiles(const ldpc_graph &g, int32_t B, int32_t chunk) {
+    const int32_t nt = (int32_t)tiles_of(B);
+    if (chunk == 0) return nt;
+    if (chunk > 0) return chunk < nt ? chunk : nt;
+    const double per_tile = (double)kTile * 4.0 * (2.0 * g.n + (double)g.E);
+    const double k = kChunkBytes / per_tile;
+    const int32_t c = k < 1.0 ? 1 : (k > nt ? nt : (int32_t)k);
+    return c;
+}
+
 size_t stream_workspace_bytes(const ldpc_graph &g, int32_t B) {
     size_t total = 0;
     carve(g, B, nullptr, &total);
@@ -422,38 +479,50 @@ int stream_decode(const ldpc_graph &g, const float *llr, int32_t B, int32_t L, u
     // unrolled check kernel when every row has 6 or 7 edges
     const int32_t regular = (g.dc_min == g.dc_max && (g.dc_max == 6 || g.dc_max == 7)) ? g.dc_max : 0;
 
+    // Chunks: all L iterations of `chunk` tiles before the next tiles, so that
+    // a chunk that fits the Infinity Cache is read from there, not from HBM,
+    // by every launch after its first.  Each frame sees the same launches in
+    // the same order as without chunks; only frames of different chunks are
+    // interleaved differently.
+    const bool tuned = g.tuning.set && g.tuning.path == 2;
+    const int32_t chunk = stream_chunk_tiles(g, B, tuned ? g.tuning.stream_chunk : -1);
     // Non-temporal message accesses: the tuning record's choice, else when one
-    // iteration's messages (4 E bytes per frame) exceed 2 GiB and so cannot
-    // stay in the caches between the two kernels anyway.
-    const bool nt_msgs = (g.tuning.set && g.tuning.path == 2 && g.tuning.stream_nt >= 0)
+    // iteration's messages of a chunk (4 E bytes per frame) exceed 2 GiB and
+    // so cannot stay in the caches between the two kernels anyway.
+    const bool nt_msgs = (tuned && g.tuning.stream_nt >= 0)
                              ? g.tuning.stream_nt == 1
-                             : (double)nt * kTile * 4.0 * (double)g.E > 2.0 * 1024 * 1024 * 1024;
+                             : (double)chunk * kTile * 4.0 * (double)g.E > 2.0 * 1024 * 1024 * 1024;
 
     k_flags_init<<<(frames + 255) / 256, 256, 0, stream>>>(B, frames, w.done, w.unsat[0], w.unsat[1], w.conv);
     k_to_tiles<<<nt * nchunks, 256, 0, stream>>>(llr, B, g.n, w.r);
     auto iterate = [&](auto nt_tag) {
         constexpr bool NT = decltype(nt_tag)::value;
-        for (int32_t t = 1; t <= L; ++t) {
-            timed_launch(K_CHECK, stream, [&] {
+        for (int32_t c0 = 0; c0 < nt; c0 += chunk) {
+            // the chunk's tiles c0 .. c0 + ct - 1: every array offset to its first tile
+            const int32_t ct = chunk < nt - c0 ? chunk : nt - c0;
+            const size_t fo = (size_t)c0 * kTile;
+            float *r = w.r + fo * g.n, *s = w.s + fo * g.n, *eta = w.eta + fo * (size_t)g.E;
+            uint32_t *done = w.done + fo, *u[2] = {w.unsat[0] + fo, w.unsat[1] + fo};
+            int32_t *conv = w.conv + fo;
+            for (int32_t t = 1; t <= L; ++t) {
                 if (regular == 6)
-                    k_check_dc<6, kRowsPerWave, NT><<<nt * row_blocks_dc, 64 * waves, 0, stream>>>(
-                        g.col_idx, g.row_class, g.m, g.n, g.E, row_blocks_dc, w.r, w.s, w.eta, w.done, w.unsat[t & 1],
-                        t, alpha, beta, ncls);
+                    timed_launch(K_CHECK, k_check_dc<6, kRowsPerWave, NT>, ct * row_blocks_dc, 64 * waves, 0, stream,
+                                 g.col_idx, g.row_class, g.m, g.n, g.E, row_blocks_dc, r, s, eta, done, u[t & 1], t,
+                                 alpha, beta, ncls);
                 else if (regular == 7)
-                    k_check_dc<7, kRowsPerWave, NT><<<nt * row_blocks_dc, 64 * waves, 0, stream>>>(
-                        g.col_idx, g.row_class, g.m, g.n, g.E, row_blocks_dc, w.r, w.s, w.eta, w.done, w.unsat[t & 1],
-                        t, alpha, beta, ncls);
+                    timed_launch(K_CHECK, k_check_dc<7, kRowsPerWave, NT>, ct * row_blocks_dc, 64 * waves, 0, stream,
+                                 g.col_idx, g.row_class, g.m, g.n, g.E, row_blocks_dc, r, s, eta, done, u[t & 1], t,
+                                 alpha, beta, ncls);
                 else
-                    k_check<NT><<<nt * row_blocks, 64 * waves, 0, stream>>>(
-                        g.row_ptr, g.col_idx, g.row_class, g.m, g.n, g.E, B, row_blocks, w.r, w.s, w.eta, w.done,
-                        w.unsat[t & 1], t, alpha, beta, ncls);
-            });
-            timed_launch(K_BIT, stream, [&] {
-                k_bit<kColsPerWave, NT><<<nt * col_blocks, 64 * waves, 0, stream>>>(
-                    g.col_ptr, g.csc_edge, g.n, g.E, col_blocks, w.r, w.s, w.eta, w.done, w.unsat[t & 1],
-                    w.unsat[(t + 1) & 1], w.conv, t,
-                    (period > 0 && (t - 1) % period == 0) ? 1 : 0); // is the decision of iteration t - 1 tested?
-            });
+                    timed_launch(K_CHECK, k_check<NT>, ct * row_blocks, 64 * waves, 0, stream, g.row_ptr, g.col_idx,
+                                 g.row_class, g.m, g.n, g.E, row_blocks, r, s, eta, done, u[t & 1], t, alpha, beta,
+                                 ncls);
+                // is the decision of iteration t - 1 tested?
+                const int32_t test_now = (period > 0 && (t - 1) % period == 0) ? 1 : 0;
+                timed_launch(K_BIT, k_bit<kColsPerWave, NT>, ct * col_blocks, 64 * waves, 0, stream, g.col_ptr,
+                             g.csc_edge, g.n, g.E, col_blocks, r, s, eta, done, u[t & 1], u[(t + 1) & 1], conv, t,
+                             test_now);
+            }
         }
     };
     if (nt_msgs)
@@ -658,15 +727,11 @@ int dense_decode(const ldpc_graph &g, const float *llr, int32_t B, int32_t L, ui
     k_flags_init<<<(frames + 255) / 256, 256, 0, stream>>>(B, frames, w.done, w.unsat[0], w.unsat[1], w.conv);
     k_to_tiles<<<nt * nchunks, 256, 0, stream>>>(llr, B, g.n, w.r);
     for (int32_t t = 1; t <= L; ++t) {
-        timed_launch(K_DENSE_ROW, stream, [&] {
-            k_dense_row<<<nt * row_blocks, 64 * waves, 0, stream>>>(g.dense_h, g.m, g.n, row_blocks, w.r, w.s, w.eta,
-                                                                    w.done, w.unsat[t & 1], t);
-        });
-        timed_launch(K_DENSE_COL, stream, [&] {
-            k_dense_col<<<nt * col_blocks, 64 * waves, 0, stream>>>(
-                g.m, g.n, col_blocks, w.r, w.s, w.eta, w.done, w.unsat[t & 1], w.unsat[(t + 1) & 1], w.conv, t,
-                (period > 0 && (t - 1) % period == 0) ? 1 : 0);
-        });
+        timed_launch(K_DENSE_ROW, k_dense_row, nt * row_blocks, 64 * waves, 0, stream, g.dense_h, g.m, g.n, row_blocks,
+                     w.r, w.s, w.eta, w.done, w.unsat[t & 1], t);
+        const int32_t test_now = (period > 0 && (t - 1) % period == 0) ? 1 : 0;
+        timed_launch(K_DENSE_COL, k_dense_col, nt * col_blocks, 64 * waves, 0, stream, g.m, g.n, col_blocks, w.r, w.s,
+                     w.eta, w.done, w.unsat[t & 1], w.unsat[(t + 1) & 1], w.conv, t, test_now);
     }
     uint32_t *unsat_final = w.unsat[(L + 1) & 1];
     k_dense_syndrome<<<nt * row_blocks, 64 * waves, 0, stream>>>(g.dense_h, g.m, g.n, row_blocks,

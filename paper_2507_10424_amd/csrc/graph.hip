@@ -225,7 +225,7 @@ int build(const uint8_t *H, int32_t m, int32_t n, hipStream_t s, ldpc_graph *g) 
         for (int32_t i = 0; i < m; ++i) h_class[i] = h_row[i] ? rank[h_row[i]] : -1;
 
         if (dalloc(&g->row_ptr, m + 1) != hipSuccess || dalloc(&g->col_idx, E) != hipSuccess ||
-            dalloc(&g->col_ptr, n + 1) != hipSuccess || dalloc(&g->csc_edge, E + 8) != hipSuccess || // 8 entries of padding: readers load groups of 8
+            dalloc(&g->col_ptr, n + 9) != hipSuccess || dalloc(&g->csc_edge, E + 8) != hipSuccess || // 8 entries of padding: readers load groups of 8
             hipMemsetAsync(g->csc_edge + E, 0, 8 * sizeof(int32_t), s) != hipSuccess ||
             dalloc(&g->row_class, m) != hipSuccess || dalloc(&g->edge_pos, E) != hipSuccess) {
             fail(LDPC_ENOMEM);
@@ -249,7 +249,7 @@ int build(const uint8_t *H, int32_t m, int32_t n, hipStream_t s, ldpc_graph *g) 
             fail(LDPC_EHIP);
             break;
         }
-        std::vector<int32_t> h_colptr(n + 1);
+        std::vector<int32_t> h_colptr(n + 9);
         int32_t dvmax = 0;
         int64_t acc = 0;
         for (int32_t j = 0; j < n; ++j) {
@@ -257,10 +257,10 @@ int build(const uint8_t *H, int32_t m, int32_t n, hipStream_t s, ldpc_graph *g) 
             acc += h_col[j];
             dvmax = std::max(dvmax, h_col[j]);
         }
-        h_colptr[n] = (int32_t)acc;
+        for (int32_t j = n; j < n + 9; ++j) h_colptr[j] = (int32_t)acc; // col_ptr[n] and 8 entries of padding
         g->dv_max = dvmax;
         g->dv_min = *std::min_element(h_col.begin(), h_col.end());
-        if (hipMemcpyAsync(g->col_ptr, h_colptr.data(), sizeof(int32_t) * (n + 1), hipMemcpyHostToDevice, s) !=
+        if (hipMemcpyAsync(g->col_ptr, h_colptr.data(), sizeof(int32_t) * (n + 9), hipMemcpyHostToDevice, s) !=
             hipSuccess) {
             fail(LDPC_EHIP);
             break;

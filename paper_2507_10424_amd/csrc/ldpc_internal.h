@@ -1,10 +1,12 @@
 // Internal declarations of libldpc (not part of the C-ABI).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
 #include <cstdint>
+#include <tuple>
 #include <vector>
 
 #include "ldpc.h"
@@ -23,7 +25,7 @@ struct ldpc_graph {
     std::vector<int32_t> class_degrees; // distinct nonzero row degrees, ascending
     int32_t *row_ptr = nullptr;   // m + 1
     int32_t *col_idx = nullptr;   // E: bit of each edge
-    int32_t *col_ptr = nullptr;   // n + 1
+    int32_t *col_ptr = nullptr;   // n + 1 (+ 8 padding entries equal to E)
     int32_t *csc_edge = nullptr;  // E (+ 8 padding entries): CSR edge number of the k-th CSC entry
     int32_t *row_class = nullptr; // m: degree class of the row (-1 for degree 0)
     int32_t *edge_pos = nullptr;  // E: CSC slot of each CSR edge (inverse of csc_edge)
@@ -42,6 +44,7 @@ struct ldpc_graph {
         int waves_per_simd = 0; // on-chip register budget: 0 compiler's, 4 at least 4 waves per SIMD
         int stream_waves = 4; // wavefronts per workgroup of the streaming kernels
         int stream_nt = -1;   // non-temporal message accesses: 1 yes, 0 no, -1 by size
+        int stream_chunk = -1; // tiles per chunk of the streaming path: 0 all, -1 by size
     } tuning;
 };
 
@@ -59,6 +62,9 @@ size_t stream_workspace_bytes(const ldpc_graph &g, int32_t B);
 int stream_decode(const ldpc_graph &g, const float *llr, int32_t B, int32_t L, uint32_t flags,
                   const float *alpha, const float *beta, int32_t T, uint8_t *bits, float *post,
                   int32_t *iters, uint8_t *ok, void *ws, size_t ws_bytes, hipStream_t stream);
+// Tiles of 64 frames per chunk of the streaming decoder for a batch of B
+// frames: chunk 0 = all tiles, k > 0 = at most k, -1 = by size.
+int32_t stream_chunk_tiles(const ldpc_graph &g, int32_t B, int32_t chunk);
 
 // On-chip (LDS-resident) decoder: whether the graph fits, workspace, launch.
 bool onchip_fits(const ldpc_graph &g);
@@ -87,22 +93,27 @@ enum KernelId { K_CHECK = 0, K_BIT = 1, K_ONCHIP = 2, K_DENSE_ROW = 3, K_DENSE_C
 bool timing_on();
 void timing_record(int kid, hipEvent_t a, hipEvent_t b);
 
-// Launch `fn` (which enqueues one kernel on `s`); when timing is enabled,
-// bracket it with two events on the same stream.
-template <class F> inline void timed_launch(int kid, hipStream_t s, F &&fn) {
-    if (!timing_on()) {
-        fn();
+// Launch `kernel` on `s`.  When timing is enabled the launch goes through
+// hipExtLaunchKernel with two HIP events that take the start and end
+// timestamps of that dispatch itself (no event packets between kernels).
+template <class... P, class... A>
+inline void timed_launch(int kid, void (*kernel)(P...), dim3 grid, dim3 block, uint32_t lds, hipStream_t s,
+                         A... a) {
+    static_assert(sizeof...(P) == sizeof...(A), "argument count");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (timing_on() && hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
+        std::tuple<P...> args{P(a)...};
+        void *ptrs[sizeof...(P)];
+        std::apply([&](auto &...x) {
+            size_t i = 0;
+            ((ptrs[i++] = (void *)&x), ...);
+        }, args);
+        (void)hipExtLaunchKernel((const void *)kernel, grid, block, ptrs, lds, s, e0, e1, 0);
+        timing_record(kid, e0, e1);
         return;
     }
-    hipEvent_t a = nullptr, b = nullptr;
-    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
-        fn();
-        return;
-    }
-    (void)hipEventRecord(a, s);
-    fn();
-    (void)hipEventRecord(b, s);
-    timing_record(kid, a, b);
+    if (e0) (void)hipEventDestroy(e0);
+    kernel<<<grid, block, lds, s>>>(a...);
 }
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }

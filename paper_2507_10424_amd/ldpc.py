@@ -48,7 +48,7 @@ class LdpcTuning(ctypes.Structure):
     """struct ldpc_tuning of include/ldpc.h"""
     _fields_ = [("path", ctypes.c_int32), ("variant", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32),
                 ("stream_waves", ctypes.c_int32), ("waves_per_simd", ctypes.c_int32), ("ms", ctypes.c_float),
-                ("stream_nt", ctypes.c_int32)]
+                ("stream_nt", ctypes.c_int32), ("stream_chunk", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -446,11 +446,11 @@ class CapturedDecode:
 
 
 def set_tuning(g: Graph, path: int | None = None, variant: int = -1, wg_per_cu: int = 0, stream_waves: int = 4,
-               waves_per_simd: int = 0, stream_nt: int = -1):
+               waves_per_simd: int = 0, stream_nt: int = -1, stream_chunk: int = -1):
     """ldpc_graph_set_tuning; path None clears the record."""
     lib = load_library()
     t = None if path is None else ctypes.byref(LdpcTuning(path, variant, wg_per_cu, stream_waves, waves_per_simd,
-                                                          0.0, stream_nt))
+                                                          0.0, stream_nt, stream_chunk))
     st = lib.ldpc_graph_set_tuning(g.handle, t)
     if st:
         raise LdpcError(st, "ldpc_graph_set_tuning")

@@ -78,3 +78,53 @@ def test_four_slot_variants_ragged(tdev, B):
             out = ldpc.minsum_decode(g, torch.from_numpy(llr_np).to(dev), 25)
             torch.cuda.synchronize()
             assert_parity(tuple(t.cpu().numpy() for t in out), ref, f"variant {v} wpc {wpc} B {B}")
+
+
+def test_stream_chunks_agree(tdev):
+    """Chunked streaming (all iterations of a group of 64-frame tiles before
+    the next group) decodes every frame like the oracle, for chunk sizes that
+    divide the tiles, leave a ragged last chunk, exceed them, and by size;
+    with the unrolled check kernel, the general one, learned weights and a
+    codeword-test period."""
+    torch, dev = tdev
+    from paper_2507_10424_amd import ldpc
+    import oracle
+    H = wl.regular_ldpc(1024, 512, 3, 6, seed=2)
+    g = ldpc.build_graph(torch.from_numpy(H).to(dev))
+    llr_np = wl.bpsk_awgn_llr(None, 1.75, 0.5, seed=33, n=1024, batch=900)  # 15 tiles, the last ragged
+    llr = torch.from_numpy(llr_np).to(dev)
+    ref = oracle_decode(H, llr_np, 40)
+    ref_p3 = oracle_decode(H, llr_np, 40, ldpc.check_period(3))
+    for chunk, nt in itertools.product((1, 2, 4, 7, 15, 100, 0, -1), (0, 1)):
+        ldpc.set_tuning(g, 2, stream_waves=4, stream_nt=nt, stream_chunk=chunk)
+        assert ldpc.get_tuning(g)["stream_chunk"] == chunk
+        out = ldpc.minsum_decode(g, llr, 40)
+        torch.cuda.synchronize()
+        assert_parity(tuple(t.cpu().numpy() for t in out), ref, f"chunk {chunk} non-temporal {nt}")
+        if chunk in (4, -1):
+            out = ldpc.minsum_decode(g, llr, 40, flags=ldpc.check_period(3))
+            torch.cuda.synchronize()
+            assert_parity(tuple(t.cpu().numpy() for t in out), ref_p3, f"chunk {chunk} period 3")
+
+    Hi = wl.random_irregular_code(300, 150, seed=8, dv_choices=(0, 2, 3, 4, 6))
+    gi = ldpc.build_graph(torch.from_numpy(Hi).to(dev))
+    rng = np.random.default_rng(9)
+    x_np = rng.normal(0.8, 1.3, size=(333, 300)).astype(np.float32)
+    C = oracle.check_degrees(Hi).size
+    T = 15
+    alpha = rng.uniform(0.5, 1.2, size=(T, C)).astype(np.float32)
+    beta = rng.uniform(0.0, 0.4, size=(T, C)).astype(np.float32)
+    ref_i = oracle_decode(Hi, x_np, 30)
+    ref_n = oracle_decode(Hi, x_np, T, 0, alpha, beta)
+    x = torch.from_numpy(x_np).to(dev)
+    for chunk in (1, 3, -1):
+        ldpc.set_tuning(gi, 2, stream_waves=2, stream_chunk=chunk)
+        out = ldpc.minsum_decode(gi, x, 30)
+        torch.cuda.synchronize()
+        assert_parity(tuple(t.cpu().numpy() for t in out), ref_i, f"irregular chunk {chunk}")
+        out = ldpc.nms_decode(gi, x, T, torch.from_numpy(alpha).to(dev), torch.from_numpy(beta).to(dev))
+        torch.cuda.synchronize()
+        assert_parity(tuple(t.cpu().numpy() for t in out), ref_n, f"irregular nms chunk {chunk}")
+    with pytest.raises(ldpc.LdpcError) as e:
+        ldpc.set_tuning(gi, 2, stream_chunk=-2)
+    assert e.value.status == -1
