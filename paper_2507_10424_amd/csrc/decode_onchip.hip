@@ -170,6 +170,10 @@ template <int DC, bool RX, int DV, bool CX, int RPT, int CPT, int F, bool NMS>
 __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t early, unsigned char *lds) {
     typedef typename Vec<F>::type V;
     constexpr uint32_t kEnt = sizeof(V); // bytes of one LDS entry (F floats)
+    // read all s (messages) of the check (bit) pass up front when that takes
+    // at most 32 registers
+    constexpr bool kPrefetchS = RPT > 1 && RPT * DC * F <= 32;
+    constexpr bool kPrefetchEta = CPT > 1 && CPT * DV * F <= 32;
     const int32_t *__restrict__ row_ptr = J.row_ptr;
     const uint32_t *__restrict__ edge_tab = J.edge_tab;
     const int32_t *__restrict__ col_ptr = J.col_ptr;
@@ -270,6 +274,17 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
         if (!live) break;
 
         // ---- check pass -------------------------------------------------------
+        // When the registers allow, the s values of all own rows are read
+        // before the first row's messages are written (the compiler cannot
+        // move a read of s above an LDS write it cannot tell apart from it),
+        // so the reads of later rows overlap the work of earlier ones.
+        V svp[RPT][DC];
+        if constexpr (kPrefetchS) {
+#pragma unroll
+            for (int r = 0; r < RPT; ++r)
+#pragma unroll
+                for (int k = 0; k < DC; ++k) svp[r][k] = lds_ld<V>(lds, sa[r][k]);
+        }
         uint32_t umask = 0;
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
@@ -277,7 +292,7 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
             const bool rowv = RX ? (tid + r * nt < m) : deg[r] > 0; // RX: recomputed, saves a register
             V sv[DC];
 #pragma unroll
-            for (int k = 0; k < DC; ++k) sv[k] = lds_ld<V>(lds, sa[r][k]);
+            for (int k = 0; k < DC; ++k) sv[k] = kPrefetchS ? svp[r][k] : lds_ld<V>(lds, sa[r][k]);
 #pragma unroll
             for (int q = 0; q < F; ++q) {
                 // RX: every edge of a real row is valid; rows past m compute
@@ -384,6 +399,22 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
         }
 
         // ---- bit pass -------------------------------------------------------------
+        // As in the check pass: when the registers allow, the messages of all
+        // own bits are read before the first s is written.  Bits past n read
+        // a valid slot (bit 0's, or the padding slot) and write nothing.
+        V evp[CPT][DV];
+        if constexpr (kPrefetchEta) {
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) {
+                const int32_t j = tid + c * nt;
+                const uint32_t base =
+                    eta0 + kEnt * (CX ? (uint32_t)(DV * (j < n ? j : 0)) : (ckd[c] & 0xffffu));
+                const int32_t dv = CX ? DV : (int32_t)(ckd[c] >> 16);
+#pragma unroll
+                for (int k = 0; k < DV; ++k)
+                    evp[c][k] = lds_ld<V>(lds, base + kEnt * (uint32_t)(CX || k < dv ? k : 0));
+            }
+        }
 #pragma unroll
         for (int c = 0; c < CPT; ++c) {
             const int32_t j = tid + c * nt;
@@ -395,7 +426,7 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
                 V ev[DV];
 #pragma unroll
                 for (int k = 0; k < DV; ++k)
-                    ev[k] = lds_ld<V>(lds, base + kEnt * (uint32_t)(CX || k < dv ? k : 0));
+                    ev[k] = kPrefetchEta ? evp[c][k] : lds_ld<V>(lds, base + kEnt * (uint32_t)(CX || k < dv ? k : 0));
                 V acc = (CX || 0 < dv) ? ev[0] : vzero<V>();
 #pragma unroll
                 for (int k = 1; k < DV; ++k)
