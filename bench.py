@@ -31,20 +31,26 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # 32-bit VALU lane-ops/s: 256 CUs x 64
 # HBM bytes per launch of the dominant kernel, measured with rocprofv3
 # FETCH_SIZE and WRITE_SIZE (each in a run of its own, scaled by a plain copy:
 # FETCH x 2.000, WRITE x 1.000), averaged over the launches of one step.  Each
-# entry holds the hash of the kernel source it was taken with; once that file
-# changes the figure no longer applies and `traffic` is reported as null.
-# Summaries: profiles/hbm_bytes_qc64800_regular1024.md.
+# entry holds the hash of the kernel source it was taken with and, for the
+# streaming kernels, the launch choices that fix how many frames one launch
+# covers (path, non-temporal messages, chunk); once the source changes, or
+# the run uses other choices, the figure no longer applies and `traffic` is
+# reported as null.  Summaries: profiles/hbm_bytes_qc64800_regular1024.md.
 MEASURED_TRAFFIC = {
-    ("regular1024", "onchip"): {"bytes": 608518955, "source": "decode_onchip.hip", "sha256_16": "112b8e8d07ecf470"},
-    ("qc64800", "check"): {"bytes": 10301304363, "source": "decode_stream.hip", "sha256_16": "e635104923181df8"},
-    ("qc64800", "bit"): {"bytes": 5691632051, "source": "decode_stream.hip", "sha256_16": "e635104923181df8"},
+    ("regular1024", "onchip"): {"bytes": 608556143, "source": "decode_onchip.hip", "sha256_16": "79bb6df2e210b100"},
+    ("qc64800", "check"): {"bytes": 322730955, "source": "decode_stream.hip", "sha256_16": "20f0d0866439769e",
+                           "tuning": {"path": 2, "stream_nt": 0, "stream_chunk": -1}},
+    ("qc64800", "bit"): {"bytes": 178164744, "source": "decode_stream.hip", "sha256_16": "20f0d0866439769e",
+                         "tuning": {"path": 2, "stream_nt": 0, "stream_chunk": -1}},
 }
 
 
-def measured_traffic(config: str, kernel: str):
+def measured_traffic(config: str, kernel: str, tuning=None):
     import hashlib
     rec = MEASURED_TRAFFIC.get((config, kernel))
     if rec is None:
+        return None
+    if "tuning" in rec and (tuning is None or any(tuning.get(k) != v for k, v in rec["tuning"].items())):
         return None
     path = os.path.join(ROOT, "paper_2507_10424_amd", "csrc", rec["source"])
     try:
@@ -282,7 +288,7 @@ def main():
         peak = VALU_PEAK_TOPS
         io = float(frames_step * (9 * n + 5))
         roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "Tops/s",
-                    "frac": round(achieved / peak, 4), "traffic": measured_traffic(args.config, dom), "kernel": dom,
+                    "frac": round(achieved / peak, 4), "traffic": measured_traffic(args.config, dom, tuning), "kernel": dom,
                     "lane_ops_per_frame_iter": ops_fi,
                     "kernel_ms_per_launch": round(dom_ms / dom_launches, 4), "launches_per_step": dom_launches,
                     "hbm_io_gb_s": round(io / (dom_ms * 1e-3) / 1e9, 1)}
@@ -292,7 +298,7 @@ def main():
         else:
             algo = float((its * (4 * E + 8 * n)).sum())
         achieved = algo / (dom_ms * 1e-3) / 1e9
-        traffic = measured_traffic(args.config, dom)
+        traffic = measured_traffic(args.config, dom, tuning)
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                     "traffic_over_algorithmic": (round(traffic / (algo / dom_launches), 3) if traffic else None),
