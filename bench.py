@@ -334,6 +334,44 @@ def main():
             mism += int(np.any(gb != ob, axis=1).sum()) + int((gi != oi).sum())
         cpu["gpu_mismatches_on_sample"] = mism
 
+    # A streaming decode in chunks keeps each chunk's state in the Infinity
+    # Cache; the same step decoding the whole batch at once (every launch
+    # streams all frames' state through HBM) is timed beside it.
+    whole = None
+    if tuning is not None and tuning.get("path") == 2 and tuning.get("stream_chunk") != 0:
+        ref_out = [(o[0].clone(), o[2].clone()) for o in outs]
+        ldpc.set_tuning(g, 2, stream_waves=tuning["stream_waves"], stream_nt=-1, stream_chunk=0)
+        step()
+        torch.cuda.synchronize()
+        ev0.record()
+        step()
+        ev1.record()
+        torch.cuda.synchronize()
+        wms = ev0.elapsed_time(ev1)
+        lib.ldpc_timing_enable(1)
+        step()
+        torch.cuda.synchronize()
+        wk = {}
+        for kid, kname in [(0, "check"), (1, "bit")]:
+            ms_k, cnt = ctypes.c_double(), ctypes.c_int64()
+            lib.ldpc_timing_read(kid, ctypes.byref(ms_k), ctypes.byref(cnt))
+            wk[kname] = (ms_k.value, cnt.value)
+        lib.ldpc_timing_enable(0)
+        wits = torch.cat([o[2].to(torch.int64) for o in outs]).to(torch.float64)
+        walgo = float(((wits >= 1).double() * (4 * E + 4 * n) + (wits - 1).clamp(min=0) * (8 * E + 4 * n)).sum())
+        whole = {"stream_chunk": 0, "coded_gbit_s": round(frames_step * n / (wms * 1e-3) / 1e9, 3),
+                 "ms_per_step": round(wms, 3),
+                 "check_kernel_ms_per_launch": round(wk["check"][0] / max(wk["check"][1], 1), 4),
+                 "check_hbm_frac": round(walgo / (wk["check"][0] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                 "outputs_equal_chunked": all(torch.equal(a[0], o[0]) and torch.equal(a[1], o[2])
+                                              for a, o in zip(ref_out, outs))}
+        del ref_out
+        ldpc.set_tuning(g, 2, variant=tuning["variant"], wg_per_cu=tuning["wg_per_cu"],
+                        stream_waves=tuning["stream_waves"], waves_per_simd=tuning["waves_per_simd"],
+                        stream_nt=tuning["stream_nt"], stream_chunk=tuning["stream_chunk"])
+        log(f"[bench] whole batch per launch (no chunks): {whole['coded_gbit_s']} Gbit/s, "
+            f"check HBM frac {whole['check_hbm_frac']}")
+
     # The same workload on the HBM-resident streaming path (one timed step),
     # for its share of HBM bandwidth on this code.
     stream_alt = None
@@ -399,7 +437,7 @@ def main():
                    "tuning": tuning},
         "edge_msg_per_s": edge_msgs, "info_gbit_s": round(gbits * k_info / n, 3) if k_info else None,
         "mean_iters": round(tot_iters / frames_step, 3), "per_point": per_point,
-        "roofline": roofline, "cpu_baseline": cpu, "hbm_resident_path": stream_alt, "nms_vs_plain": nms,
+        "roofline": roofline, "cpu_baseline": cpu, "hbm_resident_path": stream_alt, "whole_batch_stream": whole, "nms_vs_plain": nms,
         "dense_ablation": dense, "paper_context": PAPER_CONTEXT,
     }
     print(json.dumps(line), flush=True)
