@@ -174,6 +174,9 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
     // at most 32 registers
     constexpr bool kPrefetchS = RPT > 1 && RPT * DC * F <= 32;
     constexpr bool kPrefetchEta = CPT > 1 && CPT * DV * F <= 32;
+    // keep the channel LLRs of every slot's next frame in registers, read
+    // ahead, when that takes at most 8 registers
+    constexpr bool kAheadLLR = CPT * F <= 8;
     const int32_t *__restrict__ row_ptr = J.row_ptr;
     const uint32_t *__restrict__ edge_tab = J.edge_tab;
     const int32_t *__restrict__ col_ptr = J.col_ptr;
@@ -242,6 +245,23 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
     }
     V eprev[RPT][DC];
     V rc[CPT];
+    // Channel LLRs of each slot's next frame (its frame number is known one
+    // refill ahead), read while the slot still decodes its current frame, so
+    // that a refill does not wait for global memory.
+    V rnx[CPT];
+    uint32_t pend = 0; // slots whose next frame's LLRs are still to be read
+    if constexpr (kAheadLLR) {
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+            const int32_t j = tid + c * nt;
+            rnx[c] = vzero<V>();
+#pragma unroll
+            for (int q = 0; q < F; ++q) {
+                const int32_t nx = __builtin_amdgcn_readfirstlane(sh->next[q][0]);
+                if (j < n && nx < B) rnx[c][q] = llr[(size_t)nx * n + j] + 0.0f; // -0 -> +0
+            }
+        }
+    }
 #pragma unroll
     for (int r = 0; r < RPT; ++r)
 #pragma unroll
@@ -272,6 +292,24 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
 #pragma unroll
         for (int q = 0; q < F; ++q) live |= fr[q] < B;
         if (!live) break;
+        if constexpr (kAheadLLR) {
+            // the next frames of the slots refilled last round (written by
+            // thread 0 before last round's closing barrier)
+            pend = __builtin_amdgcn_readfirstlane(pend);
+            if (pend) {
+#pragma unroll
+                for (int q = 0; q < F; ++q) {
+                    if (!((pend >> q) & 1u)) continue;
+                    const int32_t nx = __builtin_amdgcn_readfirstlane(sh->next[q][gen[q] & 1]);
+#pragma unroll
+                    for (int c = 0; c < CPT; ++c) {
+                        const int32_t j = tid + c * nt;
+                        rnx[c][q] = (j < n && nx < B) ? llr[(size_t)nx * n + j] + 0.0f : 0.0f;
+                    }
+                }
+                pend = 0;
+            }
+        }
 
         // ---- check pass -------------------------------------------------------
         // When the registers allow, the s values of all own rows are read
@@ -389,6 +427,7 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
         }
 
         fin = __builtin_amdgcn_readfirstlane(fin);
+        pend = fin;
         // next round's iteration numbers (the bit pass below does not use
         // them; updated here, they stay out of its divergent branches)
 #pragma unroll
@@ -435,7 +474,8 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
 #pragma unroll
                 for (int q = 0; q < F; ++q) {
                     if ((fin >> q) & 1u) {
-                        const float v = fr[q] < B ? llr[(size_t)fr[q] * n + j] + 0.0f : 0.0f;
+                        const float v =
+                            kAheadLLR ? rnx[c][q] : (fr[q] < B ? llr[(size_t)fr[q] * n + j] + 0.0f : 0.0f);
                         rc[c][q] = v;
                         sn[q] = v;
                     }
