@@ -96,17 +96,18 @@ def alu_ops_per_frame_iter(H) -> int:
     Per check row of degree d >= 2: d subtractions x = s - eta; the min pair
     of |x| (|x| is a free source modifier); ceil((d - 1) / 2) three-input XORs
     for the sign parity and as many for the syndrome of the previous decision;
-    per edge a compare with min0, a select of min0 / min1 and one XOR-insert of
-    the sign (3 d).  Per bit of degree dv: dv additions (dv - 1 messages and
-    r).  Everything else a kernel issues (addresses, loop control, refills,
-    reductions, LDS waits) is overhead against this count."""
+    two to fold min0, min1 and the parity sign into one word K; per edge a
+    clamp of x to [-min1, min1] and one integer subtraction from K (2 d).  Per
+    bit of degree dv: dv additions (dv - 1 messages and r).  Everything else a
+    kernel issues (addresses, loop control, refills, reductions, LDS waits) is
+    overhead against this count."""
     H = np.asarray(H)
     dr = H.sum(axis=1).astype(np.int64)
     dc = H.sum(axis=0).astype(np.int64)
     ops = 0
     for d, cnt in zip(*np.unique(dr[dr >= 2], return_counts=True)):
         d = int(d)
-        ops += int(cnt) * (d + min_pair_ops(d) + 2 * ((d - 1 + 1) // 2) + 3 * d)
+        ops += int(cnt) * (d + min_pair_ops(d) + 2 * ((d - 1 + 1) // 2) + 2 + 2 * d)
     ops += int(dc.sum())
     return ops
 

@@ -357,8 +357,8 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
                 uint32_t par = xor_all<DC>(pv), syn = xor_all<DC>(sb);
                 if (RX && !rowv) syn = 0u;
                 umask |= (syn >> 31) << q;
-                uint32_t b0 = __float_as_uint(mn0), b1 = __float_as_uint(mn1);
-                if (NMS) {
+                if constexpr (NMS) {
+                    uint32_t b0 = __float_as_uint(mn0), b1 = __float_as_uint(mn1);
                     if (tt[q] <= L && rowv) {
                         const float al = alpha[(tt[q] - 1) * ncls + rcls[r]];
                         const float be = beta[(tt[q] - 1) * ncls + rcls[r]];
@@ -366,16 +366,32 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
                         b0 = __float_as_uint(v0 > 0.0f ? v0 : 0.0f);
                         b1 = __float_as_uint(v1 > 0.0f ? v1 : 0.0f);
                     }
-                }
-                // the row's sign parity folded into both magnitudes; each edge
-                // then XORs in its own sign bit.  The empty asm keeps the
-                // compiler from moving the parity XOR back onto every edge.
-                const uint32_t sg = par & 0x80000000u;
-                uint32_t b0s = b0 ^ sg, b1s = b1 ^ sg;
-                asm("" : "+v"(b0s), "+v"(b1s));
+                    // the row's sign parity folded into both magnitudes; each
+                    // edge then XORs in its own sign bit.  The empty asm keeps
+                    // the compiler from moving the parity XOR back onto every edge.
+                    const uint32_t sg = par & 0x80000000u;
+                    uint32_t b0s = b0 ^ sg, b1s = b1 ^ sg;
+                    asm("" : "+v"(b0s), "+v"(b1s));
 #pragma unroll
-                for (int k = 0; k < DC; ++k)
-                    eprev[r][k][q] = __uint_as_float(((a[k] == mn0) ? b1s : b0s) ^ (xb[k] & 0x80000000u));
+                    for (int k = 0; k < DC; ++k)
+                        eprev[r][k][q] = __uint_as_float(((a[k] == mn0) ? b1s : b0s) ^ (xb[k] & 0x80000000u));
+                } else {
+                    // Two instructions per edge.  Clamping x to [-min1, min1]
+                    // gives sign(x) min(|x|, min1): magnitude min0 at the row's
+                    // minimum, min1 elsewhere (every other |x| is >= min1).  As
+                    // 32-bit integers, non-negative floats order like their bit
+                    // patterns and a sign bit is 2^31 modulo 2^32, so with
+                    // K = min0 + min1 + (parity sign bit), K - clamp is the other
+                    // magnitude (min1 at the minimum, min0 elsewhere) carrying the
+                    // sign parity XOR sign(x): exactly the message.  When
+                    // min1 = 0 only the sign of a zero message can differ, which
+                    // changes no s (r is never -0, and s = sum + r).
+                    const uint32_t K = __float_as_uint(mn0) + __float_as_uint(mn1) + (par & 0x80000000u);
+#pragma unroll
+                    for (int k = 0; k < DC; ++k)
+                        eprev[r][k][q] = __uint_as_float(
+                            K - __float_as_uint(__builtin_amdgcn_fmed3f(__uint_as_float(xb[k]), -mn1, mn1)));
+                }
             }
 #pragma unroll
             for (int k = 0; k < DC; ++k)
