@@ -41,6 +41,7 @@
 #include <algorithm>
 
 #include "ldpc_internal.h"
+#include "minsum_row.h"
 
 namespace ldpc {
 namespace {
@@ -68,62 +69,6 @@ size_t state_bytes(const ldpc_graph &g, int F) {
 size_t lds_bytes_for(const ldpc_graph &g, int F) { return state_bytes(g, F) + sizeof(Shared); }
 
 __global__ void k_zero_u32(uint32_t *p) { *p = 0u; }
-
-// Three-input XOR in one VALU instruction (v_bitop3_b32 with truth table
-// 0x96 = a ^ b ^ c), which the compiler does not form from XOR chains.
-__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
-    uint32_t r;
-    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "v"(c));
-    return r;
-}
-
-// XOR of N words with ceil((N - 1) / 2) instructions: three-input XORs, and
-// one two-input XOR when N is even.
-template <int N> __device__ __forceinline__ uint32_t xor_all(const uint32_t *v) {
-    if constexpr (N == 1) {
-        return v[0];
-    } else if constexpr (N == 2) {
-        return v[0] ^ v[1];
-    } else {
-        uint32_t acc = xor3(v[0], v[1], v[2]);
-#pragma unroll
-        for (int k = 3; k + 1 < N; k += 2) acc = xor3(acc, v[k], v[k + 1]);
-        if constexpr (N % 2 == 0) acc ^= v[N - 1];
-        return acc;
-    }
-}
-
-// Smallest and second smallest of N non-negative floats (min0 <= min1, equal
-// on a tie): groups of three give (min3, med3); a group joins the running pair
-// as min0 = min(m, gm), min1 = min3(max(m, gm), s, gs); single leftover values
-// join as min0 = min(m, v), min1 = med3(m, v, s).  Inputs are never NaN or
-// signalling, so the float min/max instructions are exact selections.
-template <int N> __device__ __forceinline__ void min_pair(const float *a, float &m, float &s) {
-    static_assert(N >= 1, "empty row");
-    if constexpr (N == 1) {
-        m = a[0];
-        s = __builtin_inff();
-    } else if constexpr (N == 2) {
-        m = fminf(a[0], a[1]);
-        s = fmaxf(a[0], a[1]);
-    } else {
-        m = fminf(fminf(a[0], a[1]), a[2]);
-        s = __builtin_amdgcn_fmed3f(a[0], a[1], a[2]);
-        int k = 3;
-#pragma unroll
-        for (; k + 3 <= N; k += 3) {
-            const float gm = fminf(fminf(a[k], a[k + 1]), a[k + 2]);
-            const float gs = __builtin_amdgcn_fmed3f(a[k], a[k + 1], a[k + 2]);
-            s = fminf(fminf(fmaxf(m, gm), s), gs);
-            m = fminf(m, gm);
-        }
-#pragma unroll
-        for (; k < N; ++k) {
-            s = __builtin_amdgcn_fmed3f(m, a[k], s);
-            m = fminf(m, a[k]);
-        }
-    }
-}
 
 template <class V> __device__ __forceinline__ V lds_ld(const unsigned char *base, uint32_t off) {
     return *reinterpret_cast<const V *>(base + off);
@@ -376,21 +321,11 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
                     for (int k = 0; k < DC; ++k)
                         eprev[r][k][q] = __uint_as_float(((a[k] == mn0) ? b1s : b0s) ^ (xb[k] & 0x80000000u));
                 } else {
-                    // Two instructions per edge.  Clamping x to [-min1, min1]
-                    // gives sign(x) min(|x|, min1): magnitude min0 at the row's
-                    // minimum, min1 elsewhere (every other |x| is >= min1).  As
-                    // 32-bit integers, non-negative floats order like their bit
-                    // patterns and a sign bit is 2^31 modulo 2^32, so with
-                    // K = min0 + min1 + (parity sign bit), K - clamp is the other
-                    // magnitude (min1 at the minimum, min0 elsewhere) carrying the
-                    // sign parity XOR sign(x): exactly the message.  When
-                    // min1 = 0 only the sign of a zero message can differ, which
-                    // changes no s (r is never -0, and s = sum + r).
-                    const uint32_t K = __float_as_uint(mn0) + __float_as_uint(mn1) + (par & 0x80000000u);
+                    // two instructions per edge (edge_message); a zero message's
+                    // sign changes no s (r is never -0, and s = sum + r)
+                    const uint32_t K = row_word(mn0, mn1, par);
 #pragma unroll
-                    for (int k = 0; k < DC; ++k)
-                        eprev[r][k][q] = __uint_as_float(
-                            K - __float_as_uint(__builtin_amdgcn_fmed3f(__uint_as_float(xb[k]), -mn1, mn1)));
+                    for (int k = 0; k < DC; ++k) eprev[r][k][q] = edge_message(__uint_as_float(xb[k]), mn1, K);
                 }
             }
 #pragma unroll

@@ -28,6 +28,7 @@
 #include <type_traits>
 
 #include "ldpc_internal.h"
+#include "minsum_row.h"
 
 namespace ldpc {
 namespace {
@@ -108,7 +109,7 @@ __global__ __launch_bounds__(256) void k_to_tiles(const float *__restrict__ llr,
     for (int k = w; k < kTile; k += kWaves) {
         const int64_t f = (int64_t)tile * kTile + k;
         const int32_t j = j0 + lane;
-        t[k][lane] = (f < B && j < n) ? llr[f * n + j] : 0.0f;
+        t[k][lane] = (f < B && j < n) ? llr[f * n + j] + 0.0f : 0.0f; // -0 -> +0: no s or x is ever -0
     }
     __syncthreads();
     float *rt = r + (size_t)tile * n * kTile;
@@ -188,8 +189,13 @@ __global__ __launch_bounds__(512) void k_check(const int32_t *__restrict__ row_p
 // The same check update for graphs whose rows all have DC edges, RPW rows
 // per wavefront: the loops are unrolled and every load of the wavefront's
 // rows is issued before any use, so it keeps 2 DC RPW requests in flight,
-// and there are RPW times fewer wavefronts to launch.
-template <int DC, int RPW, bool NT>
+// and there are RPW times fewer wavefronts to launch.  The row's two
+// smallest magnitudes come from the min3 / med3 tournament, its sign parity
+// and syndrome from XORs of sign bits (r is loaded as r + 0, so no s or x is
+// -0 and a sign bit is the sign), and plain Min-Sum messages (PLAIN) take
+// two instructions per edge (edge_message); learned weights apply to the two
+// magnitudes before the per-edge selection.
+template <int DC, int RPW, bool NT, bool PLAIN>
 __global__ __launch_bounds__(512) void k_check_dc(const int32_t *__restrict__ col_idx,
                                                   const int32_t *__restrict__ row_class, int32_t m, int32_t n,
                                                   int64_t E, int32_t row_blocks, const float *__restrict__ r,
@@ -242,41 +248,41 @@ __global__ __launch_bounds__(512) void k_check_dc(const int32_t *__restrict__ co
     for (int q = 0; q < RPW; ++q) {
         const int32_t row = row0 + q;
         if (row >= m) break;
-        float x[DC];
-        float min0 = __builtin_inff(), min1 = __builtin_inff();
-        int32_t am = -1;
-        uint32_t par = 0;
+        float x[DC], a[DC];
+        uint32_t xb[DC], sb[DC];
 #pragma unroll
         for (int k = 0; k < DC; ++k) {
-            syn ^= sj[q][k] < 0.0f ? (1u << q) : 0u;
             x[k] = (t == 1) ? sj[q][k] : sj[q][k] - ev[q][k];
-            const float a = fabsf(x[k]);
-            par ^= x[k] < 0.0f;
-            if (a < min0) {
-                min1 = min0;
-                min0 = a;
-                am = k;
-            } else if (a < min1) {
-                min1 = a;
-            }
+            a[k] = fabsf(x[k]);
+            xb[k] = __float_as_uint(x[k]);
+            sb[k] = __float_as_uint(sj[q][k]);
         }
-        if (alpha != nullptr) {
-            const int32_t c = row_class[row];
-            const float al = alpha[(t - 1) * n_classes + c], be = beta[(t - 1) * n_classes + c];
-            const float v0 = fmaf(al, min0, -be), v1 = fmaf(al, min1, -be);
-            min0 = v0 > 0.0f ? v0 : 0.0f;
-            min1 = v1 > 0.0f ? v1 : 0.0f;
-        }
+        syn |= xor_all<DC>(sb); // sign bit: parity of the row's hard decisions
+        const uint32_t par = xor_all<DC>(xb);
+        float min0, min1;
+        min_pair<DC>(a, min0, min1);
         if (act) {
             const int64_t e0 = (int64_t)row * DC;
+            if constexpr (PLAIN) {
+                const uint32_t K = row_word(min0, min1, par);
 #pragma unroll
-            for (int k = 0; k < DC; ++k) {
-                const float mag = (k == am) ? min1 : min0;
-                st_msg<NT>(&et[(size_t)(e0 + k) * kTile], (par ^ (x[k] < 0.0f ? 1u : 0u)) ? -mag : mag);
+                for (int k = 0; k < DC; ++k) st_msg<NT>(&et[(size_t)(e0 + k) * kTile], edge_message(x[k], min1, K));
+            } else {
+                const int32_t c = row_class[row];
+                const float al = alpha[(t - 1) * n_classes + c], be = beta[(t - 1) * n_classes + c];
+                const float v0 = fmaf(al, min0, -be), v1 = fmaf(al, min1, -be);
+                const uint32_t b0 = __float_as_uint(v0 > 0.0f ? v0 : 0.0f) ^ (par & 0x80000000u);
+                const uint32_t b1 = __float_as_uint(v1 > 0.0f ? v1 : 0.0f) ^ (par & 0x80000000u);
+                // the edges at the minimum take the second magnitude (on a tie
+                // the two are equal)
+#pragma unroll
+                for (int k = 0; k < DC; ++k)
+                    st_msg<NT>(&et[(size_t)(e0 + k) * kTile],
+                               __uint_as_float(((a[k] == min0) ? b1 : b0) ^ (xb[k] & 0x80000000u)));
             }
         }
     }
-    if (act && syn) unsat[f] = 1u; // some row of this wavefront is unsatisfied
+    if (act && (syn >> 31)) unsat[f] = 1u; // some row of this wavefront is unsatisfied
 }
 
 // CPW bit columns x one frame tile per wavefront.  The first 8 messages of
@@ -505,15 +511,14 @@ int stream_decode(const ldpc_graph &g, const float *llr, int32_t B, int32_t L, u
             uint32_t *done = w.done + fo, *u[2] = {w.unsat[0] + fo, w.unsat[1] + fo};
             int32_t *conv = w.conv + fo;
             for (int32_t t = 1; t <= L; ++t) {
-                if (regular == 6)
-                    timed_launch(K_CHECK, k_check_dc<6, kRowsPerWave, NT>, ct * row_blocks_dc, 64 * waves, 0, stream,
-                                 g.col_idx, g.row_class, g.m, g.n, g.E, row_blocks_dc, r, s, eta, done, u[t & 1], t,
-                                 alpha, beta, ncls);
-                else if (regular == 7)
-                    timed_launch(K_CHECK, k_check_dc<7, kRowsPerWave, NT>, ct * row_blocks_dc, 64 * waves, 0, stream,
-                                 g.col_idx, g.row_class, g.m, g.n, g.E, row_blocks_dc, r, s, eta, done, u[t & 1], t,
-                                 alpha, beta, ncls);
-                else
+                if (regular == 6 || regular == 7) {
+                    auto *fn = regular == 6 ? (alpha ? k_check_dc<6, kRowsPerWave, NT, false>
+                                                     : k_check_dc<6, kRowsPerWave, NT, true>)
+                                            : (alpha ? k_check_dc<7, kRowsPerWave, NT, false>
+                                                     : k_check_dc<7, kRowsPerWave, NT, true>);
+                    timed_launch(K_CHECK, fn, ct * row_blocks_dc, 64 * waves, 0, stream, g.col_idx, g.row_class, g.m,
+                                 g.n, g.E, row_blocks_dc, r, s, eta, done, u[t & 1], t, alpha, beta, ncls);
+                } else
                     timed_launch(K_CHECK, k_check<NT>, ct * row_blocks, 64 * waves, 0, stream, g.row_ptr, g.col_idx,
                                  g.row_class, g.m, g.n, g.E, row_blocks, r, s, eta, done, u[t & 1], t, alpha, beta,
                                  ncls);
