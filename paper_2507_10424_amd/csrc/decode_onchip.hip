@@ -23,9 +23,12 @@
 //               (|x| is a free source modifier); sign parity = XOR of the sign
 //               bits of x; then eta_e = (|x_e| == min0 ? min1 : min0) with
 //               sign bit(x_e) XOR parity (Observations 1 and 2; on a tie
-//               min1 == min0, so every edge at the minimum may take min1).
-//               The XOR of the sign bits of the s values read per row is the
-//               syndrome of the previous hard decision.
+//               min1 == min0, so every edge at the minimum may take min1),
+//               formed for plain Min-Sum as K - clamp(x_e, -min1, min1) on
+//               the bit patterns (edge_message in minsum_row.h), for learned
+//               weights by a compare and a select of the two weighted
+//               magnitudes.  The XOR of the sign bits of the s values read
+//               per row is the syndrome of the previous hard decision.
 //   barrier     the per-slot "some row unsatisfied" bits are OR-reduced.
 //   decisions   a slot whose previous decision is a codeword (or that has run
 //               L iterations) writes its outputs and is refilled.

@@ -25,6 +25,10 @@
 // The first check launch computes the syndrome of the channel decision, so a
 // frame whose channel decision is a codeword stops with 0 iterations (the
 // pre-loop test of the paper's kernel listing).
+//
+// Batches whose state exceeds the last-level (Infinity) cache are decoded in
+// chunks of whole tiles, all iterations of one chunk before the next, so that
+// every launch after a chunk's first finds its state in that cache.
 #include <type_traits>
 
 #include "ldpc_internal.h"
