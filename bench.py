@@ -123,6 +123,8 @@ def parse():
                     help="set the tuning record instead of autotuning: path,variant,wg_per_cu,stream_waves,"
                          "waves_per_simd[,stream_nt[,stream_chunk]] (as printed by a tuned run)")
     ap.add_argument("--path", default="auto", choices=["auto", "stream", "onchip"])
+    ap.add_argument("--streams", type=int, default=0,
+                    help="HIP streams the Eb/N0 batches are issued on (0: 3 on the on-chip path, else 1)")
     ap.add_argument("--check-period", type=int, default=1,
                     help="codeword test after every k-th iteration (the paper's GPU runs use 6)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
@@ -223,10 +225,36 @@ def main():
         log(f"[bench] autotuned in {time.time() - ta:.1f} s: {tuning}")
     ws = torch.empty(max(1, ldpc.workspace_bytes(g, B, flags)), dtype=torch.uint8, device=dev)
     outs = [ldpc._outputs(B, n, dev, True) for _ in llrs]
+    # The Eb/N0 batches are independent decodes.  On the on-chip path they are
+    # issued round-robin on a few HIP streams (default priority), each with its
+    # own workspace, so that one launch's last frames overlap the next launch's
+    # first ones; the streaming path keeps one stream (its chunks are sized to
+    # the Infinity Cache, which concurrent decodes would share).
+    if args.path != "auto":
+        onchip = args.path == "onchip"
+    else:
+        onchip = tuning["path"] == 1 if tuning else args.config != "qc64800"
+    nstreams = args.streams if args.streams else (min(3, len(llrs)) if onchip else 1)
+    side = [torch.cuda.Stream(device=dev) for _ in range(nstreams)] if nstreams > 1 else []
+    side_ws = [ws] + [torch.empty_like(ws) for _ in range(nstreams - 1)]
+    log(f"[bench] {nstreams} stream(s)")
+
+    def step_on(k):
+        if k <= 1:
+            for x, o in zip(llrs, outs):
+                ldpc.minsum_decode(g, x, L, flags=flags, workspace=ws, out=o)
+            return
+        cur = torch.cuda.current_stream()
+        for st in side:
+            st.wait_stream(cur)
+        for i, (x, o) in enumerate(zip(llrs, outs)):
+            with torch.cuda.stream(side[i % k]):
+                ldpc.minsum_decode(g, x, L, flags=flags, workspace=side_ws[i % k], out=o)
+        for st in side:
+            cur.wait_stream(st)
 
     def step():
-        for x, o in zip(llrs, outs):
-            ldpc.minsum_decode(g, x, L, flags=flags, workspace=ws, out=o)
+        step_on(nstreams)
 
     for _ in range(args.warmup):
         step()
@@ -261,9 +289,10 @@ def main():
     edge_msgs = 2.0 * E * tot_iters / (ms_step * 1e-3)
     k_info = (n - wl.gf2_encoder(H).rank) if W["random_cw"] else None
 
-    # per-kernel durations from HIP events on the decode stream (one more step)
+    # per-kernel durations from HIP events on the decode stream (one more
+    # step, on one stream so that no two decodes share the GPU)
     lib.ldpc_timing_enable(1)
-    step()
+    step_on(1)
     torch.cuda.synchronize()
     ktimes = {}
     for kid, kname in [(0, "check"), (1, "bit"), (2, "onchip")]:
@@ -435,7 +464,7 @@ def main():
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": W["name"], "n": n, "m": m, "edges": E, "batch": B, "batches_per_step": len(llrs),
                    "ebn0_db": W["ebn0"], "max_iter": L, "path": args.path, "check_period": args.check_period,
-                   "tuning": tuning},
+                   "tuning": tuning, "streams": nstreams},
         "edge_msg_per_s": edge_msgs, "info_gbit_s": round(gbits * k_info / n, 3) if k_info else None,
         "mean_iters": round(tot_iters / frames_step, 3), "per_point": per_point,
         "roofline": roofline, "cpu_baseline": cpu, "hbm_resident_path": stream_alt, "whole_batch_stream": whole, "nms_vs_plain": nms,

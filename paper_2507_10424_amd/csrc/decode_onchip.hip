@@ -475,24 +475,29 @@ __device__ __forceinline__ void run_v(const Job &J, int32_t L, int32_t early, un
 }
 
 
-// One graph per launch, one variant instantiated.  W > 0 asks the compiler
-// for at least W waves per SIMD (fewer registers per thread, more resident
-// waves to hide LDS latency); W = 0 leaves the register budget to it.
-template <int V, int W, bool NMS>
-__global__ __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(W > 0 ? W : 1))) void k_onchip(
-    const Job J, int32_t L, int32_t early) {
-    extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
-    run_v<V, NMS>(J, L, early, lds);
-}
-
-// Several graphs in one launch: every workgroup works through the jobs in
-// order, each until that job's frame counter is exhausted (no grid-wide
-// barrier: a workgroup moves on while others finish their last frames).
+// Jobs of one launch: every workgroup works through them in order, each
+// until that job's frame counter is exhausted (no grid-wide barrier: a
+// workgroup moves on while others finish their last frames, so the last
+// frames of one job overlap the first ones of the next).
 constexpr int kMaxJobs = 16;
 struct JobTable {
     int32_t njobs;
     Job job[kMaxJobs];
 };
+
+// One variant instantiated, one or more jobs that all use it.  W > 0 asks
+// the compiler for at least W waves per SIMD (fewer registers per thread,
+// more resident waves to hide LDS latency); W = 0 leaves the register budget
+// to it.
+template <int V, int W, bool NMS>
+__global__ __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(W > 0 ? W : 1))) void k_onchip(
+    const JobTable jt, int32_t L, int32_t early) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
+    for (int32_t c = 0; c < jt.njobs; ++c) {
+        run_v<V, NMS>(jt.job[c], L, early, lds);
+        __syncthreads();
+    }
+}
 // The widest masked variant is left out of the multi-code kernel: the
 // register demand of a kernel is that of its largest variant, and that one
 // alone would push every variant of the launch into spills.  Jobs that need
@@ -523,7 +528,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_onchip_multi(const JobTable jt,
     }
 }
 
-using KernelFn = void (*)(const Job, int32_t, int32_t);
+using KernelFn = void (*)(const JobTable, int32_t, int32_t);
 // [learned][register budget][variant]
 #define LDPC_ONCHIP_ROW(W, N)                                                                                      \
     {&k_onchip<0, W, N>, &k_onchip<1, W, N>, &k_onchip<2, W, N>, &k_onchip<3, W, N>, &k_onchip<4, W, N>,         \
@@ -649,9 +654,11 @@ int onchip_decode(const ldpc_graph &g, const float *llr, int32_t B, int32_t L, u
     if (st) return st;
     uint32_t *queue = (uint32_t *)ws;
     const int32_t early = test_period(flags);
-    const Job J = make_job(g, v, llr, B, bits, post, iters, ok, alpha, beta, queue);
+    JobTable jt{};
+    jt.njobs = 1;
+    jt.job[0] = make_job(g, v, llr, B, bits, post, iters, ok, alpha, beta, queue);
     k_zero_words<<<1, 64, 0, stream>>>(queue, 1);
-    timed_launch(K_ONCHIP, fn, grid, threads, lds, stream, J, L, early);
+    timed_launch(K_ONCHIP, fn, grid, threads, lds, stream, jt, L, early);
     return hipGetLastError() == hipSuccess ? LDPC_OK : LDPC_EHIP;
 }
 
@@ -733,16 +740,32 @@ int onchip_decode_multi(const ldpc_job *jobs, int32_t njobs, int32_t L, uint32_t
     const int32_t early = test_period(flags);
     if (frames == 0 && own.empty()) return LDPC_OK;
     k_zero_words<<<1, 64, 0, stream>>>(queues, njobs);
-    for (const Own &o : own) {
+    // Jobs with a launch of their own that use the same kernel, workgroup size,
+    // LDS size and workgroup cap (the same graph, or graphs of one shape) go
+    // into one launch of it, in order (largest first), so that each job's last
+    // frames overlap the next job's first ones.
+    std::vector<bool> placed(own.size(), false);
+    for (size_t a = 0; a < own.size(); ++a) {
+        if (placed[a]) continue;
+        JobTable ot{};
+        int t = 0;
+        size_t l = 0;
+        int64_t fr = 0;
+        for (size_t b = a; b < own.size(); ++b) {
+            if (placed[b] || own[b].fn != own[a].fn || own[b].wg_per_cu != own[a].wg_per_cu ||
+                own[b].threads != own[a].threads || own[b].lds != own[a].lds)
+                continue;
+            placed[b] = true;
+            ot.job[ot.njobs++] = own[b].J;
+            t = own[b].threads > t ? own[b].threads : t;
+            l = own[b].lds > l ? own[b].lds : l;
+            fr += own[b].J.B;
+        }
         int grid = 0;
-        const int st = launch_grid((const void *)o.fn, o.threads, o.lds, o.num_cu, o.J.B, o.wg_per_cu, &grid,
-                                   kVariants[o.J.variant].f);
+        const int st = launch_grid((const void *)own[a].fn, t, l, own[a].num_cu, fr, own[a].wg_per_cu, &grid,
+                                   kVariants[own[a].J.variant].f);
         if (st) return st;
-        const Job J = o.J;
-        const KernelFn fn = o.fn;
-        const int t = o.threads;
-        const size_t l = o.lds;
-        timed_launch(K_ONCHIP, fn, grid, t, l, stream, J, L, early);
+        timed_launch(K_ONCHIP, own[a].fn, grid, t, l, stream, ot, L, early);
     }
     if (frames > 0) {
         int grid = 0;

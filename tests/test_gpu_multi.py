@@ -131,3 +131,37 @@ def test_multi_check_period_and_no_early_exit(tdev):
         torch.cuda.synchronize()
         for k, ((H, llr), o) in enumerate(zip(inputs, outs)):
             assert_parity(tuple(t.cpu().numpy() for t in o), oracle_decode(H, llr, 30, flags), f"multi flags {flags} {k}")
+
+
+def test_big_jobs_of_one_kernel_share_a_launch(tdev):
+    """Jobs that each fill the GPU and use the same kernel run in one launch,
+    one after another with no barrier between them (a workgroup starts the
+    next job while others finish the last frames of the previous one): two
+    (3,6) codes of different sizes, several batches each, plus a small job of
+    a third code in the shared launch, all against the oracle, twice."""
+    torch, dev = tdev
+    from paper_2507_10424_amd import ldpc
+    Ha = wl.regular_ldpc(1024, 512, 3, 6, seed=2)
+    Hb = wl.regular_ldpc(2048, 1024, 3, 6, seed=6)
+    Hc = wl.random_irregular_code(120, 60, seed=5, dv_choices=(2, 3, 4))
+    ga, gb, gc = (ldpc.build_graph(torch.from_numpy(H).to(dev)) for H in (Ha, Hb, Hc))
+    spec = [(Ha, ga, 3000, 1.5), (Hb, gb, 1500, 2.0), (Ha, ga, 2600, 2.5), (Hc, gc, 77, 1.5), (Hb, gb, 1300, 1.0)]
+    jobs, inputs, refs = [], [], []
+    for k, (H, g, B, eb) in enumerate(spec):
+        llr = wl.bpsk_awgn_llr(None, eb, 0.5, seed=900 + k, n=H.shape[1], batch=B)
+        jobs.append((g, torch.from_numpy(llr).to(dev)))
+        inputs.append((H, llr))
+        refs.append(oracle_decode(H, llr, 40))
+    import ctypes
+    lib = ldpc.load_library()
+    for rep in range(2):
+        lib.ldpc_timing_enable(1)
+        outs = ldpc.minsum_decode_multi(jobs, 40)
+        torch.cuda.synchronize()
+        ms, launches = ctypes.c_double(), ctypes.c_int64()
+        assert lib.ldpc_timing_read(2, ctypes.byref(ms), ctypes.byref(launches)) == 0
+        lib.ldpc_timing_enable(0)
+        # one launch per graph for the big jobs, one shared launch for the small one
+        assert launches.value == 3
+        for k, o in enumerate(outs):
+            assert_parity(tuple(t.cpu().numpy() for t in o), refs[k], f"shared launch job {k} rep {rep}")
