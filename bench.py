@@ -166,7 +166,7 @@ def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the decoder shards frames across GPUs "
-              "by running one independent process per GPU, which this build does not launch", file=sys.stderr)
+              "by running one independent process per GPU, which this benchmark does not launch", file=sys.stderr)
         sys.exit(2)
     import torch
     if args.copy_probe:
