@@ -179,10 +179,12 @@ size_t ldpc_multi_workspace_bytes(int32_t njobs);
  * and the check period are honoured, the path flags are ignored).  Every graph
  * must fit the on-chip kernel and live on the current device.  Jobs whose
  * batch alone fills the GPU run as launches of their own kernels (with the
- * graph's tuning record); the others share one persistent launch in which
- * workgroups take frames from per-job counters, largest job (frames x edges)
- * first, and move to the next job without waiting for the others.  All
- * launches are enqueued on `stream` in this call.
+ * graph's tuning record), one launch for all such jobs of the same kernel and
+ * launch shape (the same graph, or graphs of one shape); the others share one
+ * persistent launch.  In each launch workgroups take frames from per-job
+ * counters, largest job (frames x edges) first, and move to the next job
+ * without waiting for the others.  All launches are enqueued on `stream` in
+ * this call.
  * Errors: LDPC_EINVAL (null or empty job list, null pointers in a job with
  * B > 0, B < 0, max_iter < 0), LDPC_EUNSUPPORTED (a graph does not fit, or
  * more than LDPC_MAX_JOBS jobs), LDPC_EWORKSPACE, LDPC_EHIP.
