@@ -128,3 +128,37 @@ def test_stream_chunks_agree(tdev):
     with pytest.raises(ldpc.LdpcError) as e:
         ldpc.set_tuning(gi, 2, stream_chunk=-2)
     assert e.value.status == -1
+
+
+def test_kernel_timing_changes_no_output(tdev):
+    """With per-kernel timing on, every timed kernel goes through
+    hipExtLaunchKernel with its arguments marshalled by the library; the
+    outputs must equal those of ordinary launches, and the launch counts must
+    be what the decode issued."""
+    import ctypes
+    torch, dev = tdev
+    from paper_2507_10424_amd import ldpc
+    lib = ldpc.load_library()
+    H = wl.regular_ldpc(1024, 512, 3, 6, seed=2)
+    g = ldpc.build_graph(torch.from_numpy(H).to(dev))
+    llr = torch.from_numpy(wl.bpsk_awgn_llr(None, 2.0, 0.5, seed=77, n=1024, batch=700)).to(dev)
+    Hd = wl.regular_ldpc(96, 48, 3, 6, seed=1)
+    gd = ldpc.build_graph(torch.from_numpy(Hd).to(dev))
+    llrd = torch.from_numpy(wl.bpsk_awgn_llr(None, 2.0, 0.5, seed=78, n=96, batch=300)).to(dev)
+    runs = [("onchip", lambda: ldpc.minsum_decode(g, llr, 30, flags=ldpc.LDPC_FORCE_ONCHIP), {2: 1}),
+            ("stream", lambda: ldpc.minsum_decode(g, llr, 30, flags=ldpc.LDPC_FORCE_STREAM), {0: 30, 1: 30}),
+            ("dense", lambda: ldpc.minsum_decode_dense(gd, llrd, 30), {3: 30, 4: 30})]
+    for name, fn, counts in runs:
+        ref = fn()
+        torch.cuda.synchronize()
+        assert lib.ldpc_timing_enable(1) == 0
+        got = fn()
+        torch.cuda.synchronize()
+        for kid, want in counts.items():
+            ms, n = ctypes.c_double(), ctypes.c_int64()
+            assert lib.ldpc_timing_read(kid, ctypes.byref(ms), ctypes.byref(n)) == 0
+            assert n.value == want and ms.value > 0, (name, kid, n.value)
+        assert lib.ldpc_timing_enable(0) == 0
+        for a, b in zip(ref, got):
+            if a is not None:
+                assert torch.equal(a, b), name
