@@ -5,9 +5,10 @@
 //
 // Workgroups are persistent.  Each holds F frame "slots" (F = 2 or 4, a
 // choice of the kernel variant) and decodes them in lock step, one iteration
-// per round; a slot whose frame stops takes the next frame number from an
-// atomic counter at once, so per-frame early exit wastes no rounds and the
-// graph is read from global memory only once per workgroup.
+// per round; a slot whose frame stops takes the next frame number from
+// atomic counters at once (several, so that no single address serialises
+// the workgroups), so per-frame early exit wastes no rounds and the graph is
+// read from global memory only once per workgroup.
 //
 // Ownership.  Thread `tid` owns check rows tid + r*nt (r < RPT) and bits
 // tid + c*nt (c < CPT).  It keeps in registers, for the whole launch, the LDS
@@ -62,7 +63,64 @@ struct Shared {          // small shared words, placed after s and eta
     int32_t first[kMaxF];   // first frame of each slot
     int32_t next[kMaxF][2]; // prefetched next frame of each slot, by refill parity
     uint32_t red[2];     // OR of the per-slot unsatisfied bits, by round parity
+    int32_t hc;          // thread 0: the frame counter this workgroup draws from
+    uint32_t dead;       // thread 0: counters found exhausted
 };
+
+// Frame counters.  One counter handing out every frame number would be a
+// single address that every refill of every workgroup increments atomically;
+// when frames stop after a few iterations, those atomics (one per frame, all
+// serialised at one address) bound the decoder.  So each job has kQueues
+// counters, each in a 128-byte line of its own: counter c hands out frames
+// c, c + kQueues, c + 2 kQueues, ...  A workgroup draws from one counter and
+// moves to another live one when it finds its counter exhausted, so all
+// frames are taken before any workgroup runs out.
+constexpr int kQueues = 16;
+constexpr int kQueueStride = 32; // 32-bit words between counters
+// the counters, then one word (in a line of its own) with a bit for every
+// counter some workgroup has found exhausted
+constexpr int kQueueWords = (kQueues + 1) * kQueueStride;
+
+// Frame number of the k-th value taken from counter c of nq.
+__device__ __forceinline__ int64_t frame_of(uint32_t k, int32_t c, int32_t nq) { return (int64_t)k * nq + c; }
+
+// Counters a batch of B frames uses: one per 1,024 frames, at most kQueues
+// (a small batch needs no spreading, and every counter a workgroup finds
+// exhausted costs it one atomic round trip at the end).
+inline int32_t queues_for(int32_t B) {
+    const int32_t q = B / 1024;
+    return q < 1 ? 1 : (q > kQueues ? kQueues : q);
+}
+
+// The next live counter after c, or c when none is left.
+__device__ __forceinline__ int32_t next_live(int32_t c, uint32_t dead, int32_t nq) {
+    for (int d = 1; d < nq; ++d) {
+        const int32_t x = (c + d) % nq;
+        if (!((dead >> x) & 1u)) return x;
+    }
+    return c;
+}
+
+// Records that counter c is exhausted and learns which others are, in one
+// atomic on the shared exhausted-counter word.
+__device__ __forceinline__ uint32_t mark_dead(uint32_t *queue, int32_t c, uint32_t dead) {
+    return dead | (1u << c) | atomicOr(queue + kQueues * kQueueStride, 1u << c);
+}
+
+// One thread: a frame number below B from the live counters (blocking), or B
+// when all are exhausted.  `hc` is the counter to try first (live unless all
+// are dead); each failed attempt marks at least one more counter dead, so
+// the loop ends after at most nq attempts.
+__device__ int32_t take_frame(uint32_t *queue, int32_t B, int32_t nq, int32_t &hc, uint32_t &dead) {
+    const uint32_t all = (1u << nq) - 1u;
+    while ((dead & all) != all) {
+        if ((dead >> hc) & 1u) hc = next_live(hc, dead, nq); // some counter is live
+        const int64_t f = frame_of(atomicAdd(queue + hc * kQueueStride, 1u), hc, nq);
+        if (f < B) return (int32_t)f;
+        dead = mark_dead(queue, hc, dead);
+    }
+    return B;
+}
 
 // s[n] and eta[E + 1] (one padding slot), F floats per entry, then Shared
 size_t state_bytes(const ldpc_graph &g, int F) {
@@ -103,7 +161,8 @@ struct Job {
     const float *alpha, *beta; // learned weights (T x ncls) or null
     int32_t ncls;
     int32_t variant;  // index into kVariants
-    uint32_t *queue;  // frame counter, zero before the launch
+    uint32_t *queue;  // kQueues frame counters (kQueueStride words apart), zero before the launch
+    int32_t nq;       // counters in use (queues_for(B))
 };
 
 // Decodes all frames of one job with the workgroup (see the file comment).
@@ -119,12 +178,15 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
     typedef typename Vec<F>::type V;
     constexpr uint32_t kEnt = sizeof(V); // bytes of one LDS entry (F floats)
     // read all s (messages) of the check (bit) pass up front when that takes
-    // at most 32 registers
-    constexpr bool kPrefetchS = RPT > 1 && RPT * DC * F <= 32;
+    // at most 32 registers (s: only with exact column degrees; the masked
+    // variants need those registers to stay within four waves per SIMD)
+    constexpr bool kPrefetchS = RPT > 1 && RPT * DC * F <= 32 && CX;
     constexpr bool kPrefetchEta = CPT > 1 && CPT * DV * F <= 32;
     // keep the channel LLRs of every slot's next frame in registers, read
-    // ahead, when that takes at most 8 registers
-    constexpr bool kAheadLLR = CPT * F <= 8;
+    // ahead, when that takes at most 8 registers and the column degree is
+    // exact (the masked-column variants are the ones near the 128-register
+    // budget of four waves per SIMD, which the 8 would push into spills)
+    constexpr bool kAheadLLR = CPT * F <= 8 && CX;
     const int32_t *__restrict__ row_ptr = J.row_ptr;
     const uint32_t *__restrict__ edge_tab = J.edge_tab;
     const int32_t *__restrict__ col_ptr = J.col_ptr;
@@ -141,6 +203,7 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
     const float *__restrict__ beta = J.beta;
     const int32_t ncls = J.ncls;
     uint32_t *__restrict__ queue = J.queue;
+    const int32_t nq = J.nq;
     const uint32_t eta0 = kEnt * (uint32_t)n; // byte offset of eta
     Shared *sh = reinterpret_cast<Shared *>(lds + sh_off);
     const int tid = threadIdx.x;
@@ -174,12 +237,33 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
 
     // ---- slots --------------------------------------------------------------
     if (tid == 0) {
-        const int32_t base = (int32_t)atomicAdd(queue, 2u * F);
+        // 2 F consecutive values of the home counter with one atomic; any
+        // that fall past B come from the other counters
+        int32_t hc = (int32_t)(blockIdx.x % (uint32_t)nq);
+        uint32_t dead = 0u;
+        const uint32_t k0 = atomicAdd(queue + hc * kQueueStride, 2u * F);
+        const int32_t home = hc;
+        int32_t fs[2 * F];
+#pragma unroll
+        for (int i = 0; i < 2 * F; ++i) {
+            const int64_t f = frame_of(k0 + (uint32_t)i, home, nq);
+            if (f < B) {
+                fs[i] = (int32_t)f;
+            } else {
+                if (!((dead >> home) & 1u)) {
+                    dead = mark_dead(queue, home, dead);
+                    hc = next_live(home, dead, nq);
+                }
+                fs[i] = take_frame(queue, B, nq, hc, dead);
+            }
+        }
 #pragma unroll
         for (int q = 0; q < F; ++q) {
-            sh->first[q] = base + q;
-            sh->next[q][0] = base + F + q;
+            sh->first[q] = fs[q];
+            sh->next[q][0] = fs[F + q];
         }
+        sh->hc = hc;
+        sh->dead = dead;
         sh->red[0] = sh->red[1] = 0u;
     }
     __syncthreads();
@@ -206,7 +290,7 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
 #pragma unroll
             for (int q = 0; q < F; ++q) {
                 const int32_t nx = __builtin_amdgcn_readfirstlane(sh->next[q][0]);
-                if (j < n && nx < B) rnx[c][q] = llr[(size_t)nx * n + j] + 0.0f; // -0 -> +0
+                rnx[c][q] = llr[(size_t)(nx < B ? nx : 0) * n + (j < n ? j : 0)];
             }
         }
     }
@@ -240,24 +324,6 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
 #pragma unroll
         for (int q = 0; q < F; ++q) live |= fr[q] < B;
         if (!live) break;
-        if constexpr (kAheadLLR) {
-            // the next frames of the slots refilled last round (written by
-            // thread 0 before last round's closing barrier)
-            pend = __builtin_amdgcn_readfirstlane(pend);
-            if (pend) {
-#pragma unroll
-                for (int q = 0; q < F; ++q) {
-                    if (!((pend >> q) & 1u)) continue;
-                    const int32_t nx = __builtin_amdgcn_readfirstlane(sh->next[q][gen[q] & 1]);
-#pragma unroll
-                    for (int c = 0; c < CPT; ++c) {
-                        const int32_t j = tid + c * nt;
-                        rnx[c][q] = (j < n && nx < B) ? llr[(size_t)nx * n + j] + 0.0f : 0.0f;
-                    }
-                }
-                pend = 0;
-            }
-        }
 
         // ---- check pass -------------------------------------------------------
         // When the registers allow, the s values of all own rows are read
@@ -345,6 +411,29 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
         __syncthreads();
         const uint32_t U = __builtin_amdgcn_readfirstlane(sh->red[p]);
         if (tid == 0) sh->red[p ^ 1] = 0u;
+        if constexpr (kAheadLLR) {
+            // the next frames of the slots refilled last round (stored by
+            // thread 0 in last round's decision step)
+            pend = __builtin_amdgcn_readfirstlane(pend);
+            if (pend) {
+#pragma unroll
+                for (int q = 0; q < F; ++q) {
+                    if (!((pend >> q) & 1u)) continue;
+                    const int32_t nx = __builtin_amdgcn_readfirstlane(sh->next[q][gen[q] & 1]);
+                    // Unconditional loads from a valid address (frame 0 and bit 0
+                    // stand in past B and n; a dead slot's or an absent bit's
+                    // values are never output), and no arithmetic on the value
+                    // here: anything that reads it would make the wavefront wait
+                    // for the load now instead of at the slot's next refill.
+#pragma unroll
+                    for (int c = 0; c < CPT; ++c) {
+                        const int32_t j = tid + c * nt;
+                        rnx[c][q] = llr[(size_t)(nx < B ? nx : 0) * n + (j < n ? j : 0)];
+                    }
+                }
+                pend = 0;
+            }
+        }
 
         // ---- decisions, outputs, refills --------------------------------------
         uint32_t fin = 0;
@@ -371,7 +460,13 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
                 if (ok) ok[f] = ((U >> q) & 1u) == 0u ? 1 : 0;
             }
             const int32_t nf = __builtin_amdgcn_readfirstlane(sh->next[q][gen[q] & 1]);
-            if (tid == 0) sh->next[q][(gen[q] + 1) & 1] = (int32_t)atomicAdd(queue, 1u);
+            if (tid == 0) { // the slot's frame after next
+                int32_t hc = sh->hc;
+                uint32_t dead = sh->dead;
+                sh->next[q][(gen[q] + 1) & 1] = take_frame(queue, B, nq, hc, dead);
+                sh->hc = hc;
+                sh->dead = dead;
+            }
             fr[q] = nf;
             gen[q] += 1;
 #pragma unroll
@@ -428,8 +523,8 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
 #pragma unroll
                 for (int q = 0; q < F; ++q) {
                     if ((fin >> q) & 1u) {
-                        const float v =
-                            kAheadLLR ? rnx[c][q] : (fr[q] < B ? llr[(size_t)fr[q] * n + j] + 0.0f : 0.0f);
+                        const float v = kAheadLLR ? rnx[c][q] + 0.0f // -0 -> +0
+                                                  : (fr[q] < B ? llr[(size_t)fr[q] * n + j] + 0.0f : 0.0f);
                         rc[c][q] = v;
                         sn[q] = v;
                     }
@@ -592,6 +687,7 @@ Job make_job(const ldpc_graph &g, int variant, const float *llr, int32_t B, uint
     J.ncls = (int32_t)g.class_degrees.size();
     J.variant = variant;
     J.queue = queue;
+    J.nq = queues_for(B);
     return J;
 }
 
@@ -635,7 +731,7 @@ bool onchip_kernel_spill_free(int variant, int waves_per_simd) {
 size_t onchip_workspace_bytes(const ldpc_graph &g, int32_t B) {
     (void)g;
     (void)B;
-    return 256; // frame counter
+    return 4ull * kQueueWords; // frame counters
 }
 
 int onchip_decode(const ldpc_graph &g, const float *llr, int32_t B, int32_t L, uint32_t flags, const float *alpha,
@@ -657,12 +753,14 @@ int onchip_decode(const ldpc_graph &g, const float *llr, int32_t B, int32_t L, u
     JobTable jt{};
     jt.njobs = 1;
     jt.job[0] = make_job(g, v, llr, B, bits, post, iters, ok, alpha, beta, queue);
-    k_zero_words<<<1, 64, 0, stream>>>(queue, 1);
+    k_zero_words<<<(kQueueWords + 255) / 256, 256, 0, stream>>>(queue, kQueueWords);
     timed_launch(K_ONCHIP, fn, grid, threads, lds, stream, jt, L, early);
     return hipGetLastError() == hipSuccess ? LDPC_OK : LDPC_EHIP;
 }
 
-size_t onchip_multi_workspace_bytes(int32_t njobs) { return align_up(4ull * (size_t)(njobs > 0 ? njobs : 1), 256); }
+size_t onchip_multi_workspace_bytes(int32_t njobs) {
+    return align_up(4ull * kQueueWords * (size_t)(njobs > 0 ? njobs : 1), 256);
+}
 
 int onchip_decode_multi(const ldpc_job *jobs, int32_t njobs, int32_t L, uint32_t flags, void *ws, size_t ws_bytes,
                         hipStream_t stream) {
@@ -724,7 +822,7 @@ int onchip_decode_multi(const ldpc_job *jobs, int32_t njobs, int32_t L, uint32_t
         }
         if (alone) {
             own.push_back(Own{make_job(g, v_own, jb.llr_dev, jb.B, jb.bits_dev, jb.post_dev, jb.iters_dev, jb.ok_dev,
-                                       nullptr, nullptr, queues + k),
+                                       nullptr, nullptr, queues + (size_t)k * kQueueWords),
                               fn, t_own, l_own, g.num_cu, g.tuning.set ? g.tuning.wg_per_cu : 0});
             continue;
         }
@@ -734,12 +832,12 @@ int onchip_decode_multi(const ldpc_job *jobs, int32_t njobs, int32_t L, uint32_t
         frames += jb.B;
         num_cu = g.num_cu;
         jt.job[nj++] = make_job(g, v, jb.llr_dev, jb.B, jb.bits_dev, jb.post_dev, jb.iters_dev, jb.ok_dev, nullptr,
-                                nullptr, queues + k);
+                                nullptr, queues + (size_t)k * kQueueWords);
     }
     jt.njobs = nj;
     const int32_t early = test_period(flags);
     if (frames == 0 && own.empty()) return LDPC_OK;
-    k_zero_words<<<1, 64, 0, stream>>>(queues, njobs);
+    k_zero_words<<<(njobs * kQueueWords + 255) / 256, 256, 0, stream>>>(queues, njobs * kQueueWords);
     // Jobs with a launch of their own that use the same kernel, workgroup size,
     // LDS size and workgroup cap (the same graph, or graphs of one shape) go
     // into one launch of it, in order (largest first), so that each job's last
