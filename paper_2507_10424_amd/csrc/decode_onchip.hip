@@ -186,7 +186,7 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
     // ahead, when that takes at most 8 registers and the column degree is
     // exact (the masked-column variants are the ones near the 128-register
     // budget of four waves per SIMD, which the 8 would push into spills)
-    constexpr bool kAheadLLR = CPT * F <= 8 && CX;
+    constexpr bool kAheadLLR = CPT * F <= 8 && CX && !NMS;
     const int32_t *__restrict__ row_ptr = J.row_ptr;
     const uint32_t *__restrict__ edge_tab = J.edge_tab;
     const int32_t *__restrict__ col_ptr = J.col_ptr;
