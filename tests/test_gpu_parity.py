@@ -212,3 +212,28 @@ def test_onchip_refuses_too_many_threads():
     out = ldpc.minsum_decode(g, x, 10)
     torch.cuda.synchronize()
     assert_parity(tuple(t.cpu().numpy() for t in out), oracle_decode(H, x.cpu().numpy(), 10), "n=4096 auto")
+
+
+@pytest.mark.parametrize("B", [1023, 1025, 5003, 20011])
+def test_every_frame_decoded_once(B):
+    """Frame numbers come from up to 16 counters (one per 1,024 frames) that
+    hand out interleaved frames and run dry at different times; every frame
+    must be decoded exactly once.  The outputs are prefilled with values no
+    decode produces, so a skipped frame shows; a frame decoded twice would
+    still match, but then another would be skipped."""
+    import torch
+    from paper_2507_10424_amd import ldpc
+    dev = torch.device("cuda:0")
+    H = wl.regular_ldpc(96, 48, 3, 6, seed=1)
+    llr = wl.bpsk_awgn_llr(None, 2.5, 0.5, seed=1300 + B, n=96, batch=B)
+    g = ldpc.build_graph(torch.from_numpy(H).to(dev))
+    out = ldpc._outputs(B, 96, dev, True)
+    out[0].fill_(7)
+    out[1].fill_(float("nan"))
+    out[2].fill_(-7)
+    out[3].fill_(9)
+    ldpc.minsum_decode(g, torch.from_numpy(llr).to(dev), 30, flags=ldpc.LDPC_FORCE_ONCHIP, out=out)
+    torch.cuda.synchronize()
+    got = tuple(t.cpu().numpy() for t in out)
+    assert (got[2] >= 0).all() and (got[3] <= 1).all() and (got[0] <= 1).all() and not np.isnan(got[1]).any()
+    assert_parity(got, oracle_decode(H, llr, 30), f"B={B}")
