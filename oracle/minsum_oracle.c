@@ -206,11 +206,28 @@ static void check_update(const tanner_t *g, const float *s, float *eta, float *x
             if (fabsf(x[a]) < mu) mu = fabsf(x[a]); /* planted: own magnitude in the min */
 #endif
             if (w->alpha) {
+#if ORACLE_MUTANT == 11
+                const int32_t c = i % w->n_classes; /* planted: class from the row index */
+#else
                 const int32_t c = g->row_class[i];
-                const float al = w->alpha[(int64_t)(t - 1) * w->n_classes + c];
-                const float be = w->beta[(int64_t)(t - 1) * w->n_classes + c];
+#endif
+#if ORACLE_MUTANT == 8
+                const int64_t tw = t % w->T; /* planted: the next iteration's weights */
+#else
+                const int64_t tw = t - 1;
+#endif
+                const float al = w->alpha[tw * w->n_classes + c];
+                const float be = w->beta[tw * w->n_classes + c];
+#if ORACLE_MUTANT == 9
+                const float v = fmaf(al, mu, be); /* planted: offset added */
+#else
                 const float v = fmaf(al, mu, -be);
+#endif
+#if ORACLE_MUTANT == 10
+                mu = v; /* planted: no clamp at zero */
+#else
                 mu = v > 0.0f ? v : 0.0f;
+#endif
             }
             eta[e0 + a] = sigma * mu;
         }

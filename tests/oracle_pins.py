@@ -280,6 +280,53 @@ def pin_nms_unit_weights(orc):
         assert np.array_equal(x, y)
 
 
+def pin_nms_single_checks_closed_form(orc):
+    """The learned check update on disjoint single checks of degrees 5, 3, 7
+    and 3 (rows in that order, so a row's degree class -- the rank of its
+    degree among the distinct row degrees, 3 < 5 < 7 -- differs from its row
+    index).  On a single check the extrinsic input of every iteration is the
+    channel LLR, so after t iterations (no early exit) the posterior is
+    r_j + sign product of the other r times max(alpha[t-1][c] mu - beta[t-1][c], 0),
+    mu the smallest other |r|.  Inputs and weights are multiples of 1/32 and
+    1/4 of small size, so every step is exact in binary32 and the closed form
+    is compared bit for bit.  Each (iteration, class) has its own weights,
+    and some offsets exceed alpha mu, where the message is zero."""
+    degs = (5, 3, 7, 3)
+    n = sum(degs)
+    H = np.zeros((len(degs), n), np.uint8)
+    col = 0
+    for i, d in enumerate(degs):
+        H[i, col:col + d] = 1
+        col += d
+    classes = {3: 0, 5: 1, 7: 2}
+    assert orc.check_degrees(H).tolist() == [3, 5, 7]
+    rng = np.random.default_rng(23)
+    T, C = 4, 3
+    alpha = (rng.integers(1, 8, size=(T, C)) / 4.0).astype(np.float32)  # 0.25 .. 1.75
+    beta = (rng.integers(0, 24, size=(T, C)) / 4.0).astype(np.float32)  # 0 .. 5.75
+    assert len({(a, b) for a, b in zip(alpha.ravel(), beta.ravel())}) == T * C
+    mag = rng.integers(1, 256, size=(24, n)) / 32.0  # 1/32 .. 8
+    r = (np.where(rng.random((24, n)) < 0.4, -1.0, 1.0) * mag).astype(np.float32)
+    zero_messages = 0
+    for t in range(1, T + 1):
+        bits, post, iters, _ = orc.nms_decode(H, r, t, alpha, beta, early_exit=False)
+        assert np.all(iters == t)
+        col = 0
+        for i, d in enumerate(degs):
+            c = classes[d]
+            for j in range(col, col + d):
+                others = np.delete(r[:, col:col + d], j - col, axis=1).astype(np.float64)
+                sigma = np.prod(np.where(others < 0, -1.0, 1.0), axis=1)
+                mu = np.abs(others).min(axis=1)
+                v = np.maximum(float(alpha[t - 1, c]) * mu - float(beta[t - 1, c]), 0.0)
+                zero_messages += int((v == 0).sum())
+                want = (r[:, j].astype(np.float64) + sigma * v).astype(np.float32)
+                assert np.array_equal(post[:, j], want), (t, i, j)
+                assert np.array_equal(bits[:, j], (want < 0).astype(np.uint8)), (t, i, j)
+            col += d
+    assert zero_messages > 0
+
+
 ALL_PINS = [
     pin_codewords_stop_at_iteration0,
     pin_max_iter_zero,
@@ -293,4 +340,5 @@ ALL_PINS = [
     pin_dense_map_reduce_form,
     pin_no_early_exit_runs_L,
     pin_nms_unit_weights,
+    pin_nms_single_checks_closed_form,
 ]

@@ -35,8 +35,10 @@ def test_paper_tanner_fixture():
 # 1 channel term dropped from the bit update, 2 no extrinsic subtraction,
 # 3 own sign kept in the sign product, 4 own magnitude kept in the minimum,
 # 5 slicer polarity flipped, 6 no pre-loop codeword test, 7 operands of the
-# extrinsic subtraction swapped.
-MUTANTS = [1, 2, 3, 4, 5, 6, 7]
+# extrinsic subtraction swapped; in the learned check update: 8 the next
+# iteration's weights, 9 offset added, 10 no clamp at zero, 11 degree class
+# taken from the row index.
+MUTANTS = [1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11]
 
 
 @pytest.mark.parametrize("mutant", MUTANTS)
