@@ -186,7 +186,7 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
     // ahead, when that takes at most 8 registers and the column degree is
     // exact (the masked-column variants are the ones near the 128-register
     // budget of four waves per SIMD, which the 8 would push into spills)
-    constexpr bool kAheadLLR = CPT * F <= 8 && CX && !NMS;
+    constexpr bool kAheadLLR = CPT * F <= 8 && CX && (!NMS || RX);
     const int32_t *__restrict__ row_ptr = J.row_ptr;
     const uint32_t *__restrict__ edge_tab = J.edge_tab;
     const int32_t *__restrict__ col_ptr = J.col_ptr;
@@ -374,8 +374,19 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
                 if constexpr (NMS) {
                     uint32_t b0 = __float_as_uint(mn0), b1 = __float_as_uint(mn1);
                     if (tt[q] <= L && rowv) {
-                        const float al = alpha[(tt[q] - 1) * ncls + rcls[r]];
-                        const float be = beta[(tt[q] - 1) * ncls + rcls[r]];
+                        float al, be;
+                        if constexpr (RX) {
+                            // every row has degree DC, so one class: the
+                            // weights are the workgroup's, read through the
+                            // scalar cache (constant address space) instead of
+                            // a vector load each lane waits on
+                            const int32_t wi = __builtin_amdgcn_readfirstlane((tt[q] - 1) * ncls);
+                            al = *(const __attribute__((address_space(4))) float *)(alpha + wi);
+                            be = *(const __attribute__((address_space(4))) float *)(beta + wi);
+                        } else {
+                            al = alpha[(tt[q] - 1) * ncls + rcls[r]];
+                            be = beta[(tt[q] - 1) * ncls + rcls[r]];
+                        }
                         const float v0 = fmaf(al, mn0, -be), v1 = fmaf(al, mn1, -be);
                         b0 = __float_as_uint(v0 > 0.0f ? v0 : 0.0f);
                         b1 = __float_as_uint(v1 > 0.0f ? v1 : 0.0f);

@@ -153,6 +153,30 @@ def test_nms_weights(path):
 
 
 @pytest.mark.parametrize("path", sorted(PATHS))
+def test_nms_disjoint_single_checks(path):
+    """Learned update on disjoint single checks of degrees 5, 3, 7, 3 (a row's
+    degree class differs from its row index), its own weights per iteration
+    and class, offsets that zero some messages, dyadic inputs: every step is
+    exact in binary32, so the posteriors must equal the oracle's bit for bit."""
+    degs = (5, 3, 7, 3)
+    H = np.zeros((len(degs), sum(degs)), np.uint8)
+    col = 0
+    for i, d in enumerate(degs):
+        H[i, col:col + d] = 1
+        col += d
+    rng = np.random.default_rng(23)
+    T, C = 4, 3
+    alpha = (rng.integers(1, 8, size=(T, C)) / 4.0).astype(np.float32)
+    beta = (rng.integers(0, 24, size=(T, C)) / 4.0).astype(np.float32)
+    mag = rng.integers(1, 256, size=(150, H.shape[1])) / 32.0
+    llr = (np.where(rng.random(mag.shape) < 0.4, -1.0, 1.0) * mag).astype(np.float32)
+    for t in range(1, T + 1):
+        gpu, ref = check(H, llr, t, PATHS[path] | 1, alpha, beta, what=f"nms single checks t={t} {path}")
+        assert np.array_equal(gpu[1], ref[1])
+    check(H, llr, T, PATHS[path], alpha, beta, what=f"nms single checks early exit {path}")
+
+
+@pytest.mark.parametrize("path", sorted(PATHS))
 def test_medium_code_subset(path):
     """(3,6) n=1024 code, random codewords, 4096 frames at 1.5 dB, L = 50."""
     H = wl.regular_ldpc(1024, 512, 3, 6, seed=2)
