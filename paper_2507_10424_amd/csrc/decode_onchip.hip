@@ -185,7 +185,9 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
     // keep the channel LLRs of every slot's next frame in registers, read
     // ahead, when that takes at most 8 registers and the column degree is
     // exact (the masked-column variants are the ones near the 128-register
-    // budget of four waves per SIMD, which the 8 would push into spills)
+    // budget of four waves per SIMD, which the 8 would push into spills);
+    // the learned update only with exact row degrees, where its weights sit
+    // in scalar registers and leave room for the 8
     constexpr bool kAheadLLR = CPT * F <= 8 && CX && (!NMS || RX);
     const int32_t *__restrict__ row_ptr = J.row_ptr;
     const uint32_t *__restrict__ edge_tab = J.edge_tab;
