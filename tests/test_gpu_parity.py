@@ -177,6 +177,31 @@ def test_nms_disjoint_single_checks(path):
 
 
 @pytest.mark.parametrize("path", sorted(PATHS))
+def test_nms_shipped_weights_many_refills(path):
+    """The shipped learned weights of the (3,6) n = 1024 code (one weight
+    class: the exact-degree kernels, weights read once per workgroup),
+    20,011 frames at 2.0 and 2.5 dB, so every slot refills many times and
+    each refill takes its LLRs from the look-ahead; early exit, an iteration
+    limit below T and a codeword-test period of 6."""
+    import json
+    import os
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    with open(os.path.join(root, "paper_2507_10424_amd", "weights", "nms_regular1024.json")) as f:
+        rec = json.load(f)
+    alpha = np.asarray(rec["alpha"], np.float32)
+    beta = np.asarray(rec["beta"], np.float32)
+    T = alpha.shape[0]
+    H = wl.regular_ldpc(1024, 512, 3, 6, seed=2)
+    enc = wl.gf2_encoder(H)
+    for eb, seed in ((2.0, 91), (2.5, 92)):
+        cw = enc.random_codewords(20011, seed=seed)
+        llr = wl.bpsk_awgn_llr(cw, eb, 0.5, seed=seed + 10)
+        check(H, llr, T, PATHS[path], alpha, beta, what=f"shipped weights {eb} dB {path}")
+    check(H, llr, T - 7, PATHS[path], alpha, beta, what=f"shipped weights L=T-7 {path}")
+    check(H, llr, T, PATHS[path] | (6 << 8), alpha, beta, what=f"shipped weights period 6 {path}")
+
+
+@pytest.mark.parametrize("path", sorted(PATHS))
 def test_medium_code_subset(path):
     """(3,6) n=1024 code, random codewords, 4096 frames at 1.5 dB, L = 50."""
     H = wl.regular_ldpc(1024, 512, 3, 6, seed=2)
