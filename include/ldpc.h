@@ -200,7 +200,10 @@ int ldpc_minsum_decode_multi(const ldpc_job *jobs, int32_t njobs, int32_t max_it
  *     max(fma(alpha[t-1][c], mu, -beta[t-1][c]), 0)
  * before the sign is applied.  alpha = 1, beta = 0 everywhere reproduces
  * ldpc_minsum_decode bit for bit.
- *   alpha_dev, beta_dev  T x n_classes float32 device arrays, row-major.
+ *   alpha_dev, beta_dev  T x n_classes float32 device arrays, row-major,
+ *                        owned by the caller; they must not change until the
+ *                        call's kernels have finished (they may be read through
+ *                        the scalar cache).
  *   T                    number of weight rows; requires max_iter <= T.
  * Errors: as ldpc_minsum_decode, and LDPC_EINVAL for null weights, T < 1 or
  * max_iter > T.
