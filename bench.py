@@ -133,6 +133,9 @@ def parse():
     ap.add_argument("--no-dense", action="store_true", help="skip the dense (Algorithm 2) ablation")
     ap.add_argument("--no-stream-alt", action="store_true",
                     help="skip the streaming-path measurement of the n = 1024 workload")
+    ap.add_argument("--no-c4", action="store_true", help="skip the n = 64800 block of the default line")
+    ap.add_argument("--no-multi", action="store_true", help="skip the multi-code block of the default line")
+    ap.add_argument("--no-c0", action="store_true", help="skip the n = 96 block of the default line")
     ap.add_argument("--profile-only", action="store_true", help="warmup + timed steps, no extras (for rocprofv3)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 256 MiB three times (calibrates the HBM byte counters of a profiler)")
@@ -154,8 +157,9 @@ def workload(name):
                     random_cw=False, seed_cw=0, seed_noise=500)
     if name == "multi8":
         fam = wl.qc_multi_code_family(seed=7)
+        frames = sum(c["batch"] for c in fam)
         return dict(name="8 irregular QC codes n in {576,1152,1728,2304}, rates 1/2..5/6, Z in {24,48,72,96}, "
-                         "batches 512..16384 (49152 frames), all-zero codewords at 2 dB, L=50, one launch",
+                         f"batches 512..16384 ({frames} frames), all-zero codewords at 2 dB, L=50, one call",
                     family=fam, ebn0=[2.0], L=50, seed_noise=700)
     H = wl.regular_ldpc(96, 48, 3, 6, seed=1)
     return dict(name="(3,6)-regular n=96 m=48, 1000 all-zero frames at 2 dB, L=20", H=H, batch=1000, ebn0=[2.0],
@@ -326,6 +330,11 @@ def main():
                     "frac": round(achieved / peak, 4), "traffic": measured_traffic(args.config, dom, tuning), "kernel": dom,
                     "lane_ops_per_frame_iter": ops_fi,
                     "kernel_ms_per_launch": round(dom_ms / dom_launches, 4), "launches_per_step": dom_launches,
+                    "kernel_timing": "HIP events on the launch stream, one more step issued on one stream so that "
+                                     "no two decodes overlap",
+                    "frac_timed_step": round(ops / (ms_step * 1e-3) / 1e12 / peak, 4),
+                    "frac_timed_step_note": f"the same lane-operations over the timed step ({ms_step:.3f} ms on "
+                                            f"{nstreams} streams, whose launches overlap)",
                     "hbm_io_gb_s": round(io / (dom_ms * 1e-3) / 1e9, 1)}
     else:
         if dom == "check":
@@ -342,32 +351,12 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
-        per = max(1, int(2 * 1024 / max(len(llrs), 1)))
-        # size the sample to about --cpu-seconds: probe with a few frames first
-        probe = [x[:8].cpu().numpy() for x in llrs]
-        nthreads = os.cpu_count() or 1
-        nthreads = min(nthreads, 16)
-        tp = time.time()
-        for x in probe:
-            oracle.minsum_decode(H, x, L, nthreads=1)
-        t_probe = (time.time() - tp) / (8 * len(probe))  # s per frame on one core
-        per = max(4, min(B, int(args.cpu_seconds * nthreads / max(t_probe, 1e-6) / len(llrs))))
-        sample = [x[:per].cpu().numpy() for x in llrs]
-        tc = time.time()
-        ref = [oracle.minsum_decode(H, x, L, nthreads=nthreads, check_period=args.check_period) for x in sample]
-        t_cpu = time.time() - tc
-        cpu_frames = per * len(sample)
-        cpu = {"value": round(cpu_frames * n / t_cpu / 1e9, 6), "unit": "Gbit/s", "cores": nthreads,
-               "kind": "oracle", "sample": f"first {per} frames of each of the {len(sample)} Eb/N0 batches "
-                                           f"({cpu_frames} frames, {t_cpu:.1f} s)"}
-        # parity of the timed GPU outputs on the sample
-        mism = 0
-        for (ob, op, oi, oo), o in zip(ref, outs):
-            gb = o[0][:per].cpu().numpy()
-            gi = o[2][:per].cpu().numpy()
-            mism += int(np.any(gb != ob, axis=1).sum()) + int((gi != oi).sum())
-        cpu["gpu_mismatches_on_sample"] = mism
+        # the oracle on the same frames: the first `per` frames of every Eb/N0
+        # batch, all threads of this process's CPU share, then one thread
+        samples = [x for x in llrs]
+        cpu = cpu_oracle_baseline(H, samples, L, args.cpu_seconds, args.check_period, E)
+        gpu_sample = [tuple(t[: cpu["frames_per_batch"]] for t in o) for o in outs]
+        cpu["gpu_mismatches_on_sample"] = parity_counts(gpu_sample, cpu.pop("_ref"))
 
     # A streaming decode in chunks keeps each chunk's state in the Infinity
     # Cache; the same step decoding the whole batch at once (every launch
@@ -462,6 +451,21 @@ def main():
         log(f"[bench] side measurement failed: {e}")
         nms = nms if nms is not None else {"error": str(e)}
 
+    # The other workloads, untimed by the step above: n = 64800 (HBM-resident
+    # streaming path), the eight-code family (one call), n = 96 in full.
+    c4 = multi = c0 = None
+    if args.config == "regular1024" and args.path == "auto":
+        try:
+            if not args.no_c4:
+                c4 = block_qc64800(args, dev, lib)
+            if not args.no_multi:
+                multi = multi_measure(args, workload("multi8"), dev, lib, autotune=not args.no_autotune, steps=5,
+                                      warmup=1)
+            if not args.no_c0:
+                c0 = block_regular96(args, dev)
+        except ldpc.LdpcError as e:  # report, keep the main result
+            log(f"[bench] side workload failed: {e}")
+
     line = {
         "metric": "coded Gbit/s & edge-msg/s (% HBM BW); neural vs plain Min-Sum at equal FER",
         "value": round(gbits, 3), "unit": "Gbit/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -473,9 +477,103 @@ def main():
         "edge_msg_per_s": edge_msgs, "info_gbit_s": round(gbits * k_info / n, 3) if k_info else None,
         "mean_iters": round(tot_iters / frames_step, 3), "per_point": per_point,
         "roofline": roofline, "cpu_baseline": cpu, "hbm_resident_path": stream_alt, "whole_batch_stream": whole, "nms_vs_plain": nms,
-        "dense_ablation": dense, "paper_context": PAPER_CONTEXT,
+        "dense_ablation": dense, "qc64800": c4, "multi_code": multi, "regular96": c0,
+        "paper_context": PAPER_CONTEXT,
     }
     print(json.dumps(line), flush=True)
+
+
+def host_cpu_info():
+    """CPU model, logical CPUs and the threads this process may use (its
+    affinity, capped by the thread share OMP_NUM_THREADS gives one GPU's job
+    on a shared host)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    logical = os.cpu_count() or 1
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = logical
+    share = int(os.environ.get("OMP_NUM_THREADS", "0") or 0)
+    threads = min(affinity, share) if share > 0 else affinity
+    return {"cpu_model": model, "logical_cpus": logical, "affinity_cpus": affinity,
+            "thread_share": share or None, "threads": max(1, threads)}
+
+
+def parity_counts(gpu, ref):
+    """Frames whose GPU outputs differ from the oracle's, per output: bits,
+    iteration counts and convergence flags exactly, posteriors beyond
+    1e-5 (1 + |oracle|).  gpu: per batch (bits, post, iters, ok) tensors;
+    ref: per batch the oracle's numpy tuple on the same frames."""
+    c = {"frames": 0, "bits": 0, "iters": 0, "ok": 0, "post": 0}
+    for o, (ob, op, oi, oo) in zip(gpu, ref):
+        gb, gp, gi, go = (None if t is None else t.cpu().numpy() for t in o)
+        c["frames"] += int(ob.shape[0])
+        c["bits"] += int(np.any(gb != ob, axis=1).sum())
+        c["iters"] += int((gi != oi).sum())
+        c["ok"] += int((go != oo).sum())
+        if gp is not None:
+            bad = np.abs(gp.astype(np.float64) - op) > 1e-5 * (1.0 + np.abs(op))
+            c["post"] += int(np.any(bad, axis=1).sum())
+    c["total"] = c["bits"] + c["iters"] + c["ok"] + c["post"]
+    return c
+
+
+def cpu_oracle_baseline(H, batches, L, seconds, check_period=1, E=None, alpha=None, beta=None, min_frames=4):
+    """The CPU oracle (as it stands) on a bounded sample of the same frames:
+    the first `per` frames of every batch, sized to about `seconds` of work on
+    all threads of this process's share, timed there and on one thread (a
+    smaller sample).  Returns the report and, under "_ref", the oracle's
+    outputs on the all-thread sample for the parity check."""
+    import oracle
+    info = host_cpu_info()
+    nthreads = info["threads"]
+    m, n = H.shape
+    E = int(H.sum()) if E is None else E
+    probe = [x[:4].cpu().numpy() for x in batches]
+
+    def run(xs, threads):
+        if alpha is None:
+            return [oracle.minsum_decode(H, x, L, nthreads=threads, check_period=check_period) for x in xs]
+        return [oracle.nms_decode(H, x, L, alpha, beta, nthreads=threads) for x in xs]
+
+    tp = time.time()
+    run(probe, 1)
+    t_probe = (time.time() - tp) / (4 * len(probe))  # s per frame on one thread
+    B = batches[0].shape[0]
+    per = max(min_frames, min(B, int(seconds * nthreads / max(t_probe, 1e-6) / len(batches))))
+    per = min(per, B)
+    sample = [x[:per].cpu().numpy() for x in batches]
+    tc = time.time()
+    ref = run(sample, nthreads)
+    t_all = time.time() - tc
+    per1 = max(1, min(per, int(0.3 * seconds / max(t_probe, 1e-6) / len(batches))))
+    t1 = time.time()
+    ref1 = run([x[:per1] for x in sample], 1)
+    t_one = time.time() - t1
+    frames_all, frames_one = per * len(sample), per1 * len(sample)
+    msgs_all = 2.0 * E * sum(int(r[2].sum()) for r in ref)
+    msgs_one = 2.0 * E * sum(int(r[2].sum()) for r in ref1)
+    return {"value": round(frames_all * n / t_all / 1e9, 6), "unit": "Gbit/s", "cores": nthreads, "kind": "oracle",
+            "sample": f"first {per} frames of each of the {len(sample)} batches ({frames_all} frames, {t_all:.1f} s "
+                      f"on {nthreads} threads); single thread: first {per1} of each ({frames_one} frames, "
+                      f"{t_one:.1f} s)",
+            "all_threads": {"threads": nthreads, "frames": frames_all, "seconds": round(t_all, 3),
+                            "frames_per_s": round(frames_all / t_all, 2),
+                            "coded_gbit_s": round(frames_all * n / t_all / 1e9, 6),
+                            "edge_msg_per_s": round(msgs_all / t_all, 1)},
+            "single_thread": {"threads": 1, "frames": frames_one, "seconds": round(t_one, 3),
+                              "frames_per_s": round(frames_one / t_one, 2),
+                              "coded_gbit_s": round(frames_one * n / t_one / 1e9, 6),
+                              "edge_msg_per_s": round(msgs_one / t_one, 1)},
+            "host": info, "frames_per_batch": per, "_ref": ref}
 
 
 def wilson(k: int, n: int, z: float = 1.96):
@@ -488,13 +586,13 @@ def wilson(k: int, n: int, z: float = 1.96):
     return [round(max(0.0, c - h), 6), round(min(1.0, c + h), 6)]
 
 
-def nms_vs_plain(args, W, g, llrs, cws, flags, ws):
+def nms_vs_plain(args, W, g, llrs, cws, flags, ws, path=None):
     """The learned decoder (T iterations, weights trained by train_nms.py and
     stored in the package) against plain Min-Sum (L iterations) on the same
     frames: FER with Wilson 95% intervals and coded Gbit/s of each."""
     import torch
     from paper_2507_10424_amd import ldpc
-    path = os.path.join(ROOT, "paper_2507_10424_amd", "weights", f"nms_{args.config}.json")
+    path = path or os.path.join(ROOT, "paper_2507_10424_amd", "weights", f"nms_{args.config}.json")
     if not os.path.exists(path):
         log(f"[bench] no learned weights at {path}; skipping the learned decoder")
         return None
@@ -534,6 +632,149 @@ def nms_vs_plain(args, W, g, llrs, cws, flags, ws):
     return {"weights": os.path.relpath(path, ROOT), "T": T, "train": rec.get("train"), "points": res}
 
 
+def stream_kernel_ms(lib, run):
+    """Summed event-timed milliseconds and launches of the streaming check and
+    bit kernels over one call of run()."""
+    import ctypes
+    import torch
+    lib.ldpc_timing_enable(1)
+    run()
+    torch.cuda.synchronize()
+    res = {}
+    for kid, kname in [(0, "check"), (1, "bit")]:
+        ms_k, cnt = ctypes.c_double(), ctypes.c_int64()
+        lib.ldpc_timing_read(kid, ctypes.byref(ms_k), ctypes.byref(cnt))
+        res[kname] = (ms_k.value, cnt.value)
+    lib.ldpc_timing_enable(0)
+    return res
+
+
+def stream_algo_bytes(its, E, n):
+    """Algorithmic HBM bytes of the streaming kernels for per-frame iteration
+    counts `its`: check 8E + 4n per frame-iteration (4E + 4n in iteration 1,
+    which reads no messages), bit 4E + 8n."""
+    check = float(((its >= 1).double() * (4 * E + 4 * n) + (its - 1).clamp(min=0) * (8 * E + 4 * n)).sum())
+    bit = float((its * (4 * E + 8 * n)).sum())
+    return check, bit
+
+
+def block_qc64800(args, dev, lib):
+    """The irregular QC n = 64800 workload at one Eb/N0 point (4,096 all-zero
+    frames at 1.4 dB, L = 50) on the streaming path: chunks kept in the
+    Infinity Cache (the size rule) and the whole batch in every launch
+    (every byte streamed from HBM), with the full-iteration HBM fraction of
+    each; the oracle on the first frames (all outputs compared) and timed on
+    the host; the learned decoder against plain Min-Sum on the same frames."""
+    import torch
+    from paper_2507_10424_amd import ldpc
+    from paper_2507_10424_amd import workloads as wl
+    W = workload("qc64800")
+    H = W["H"]
+    m, n = H.shape
+    B, L, eb = W["batch"], W["L"], 1.4
+    p = W["ebn0"].index(eb)
+    g = ldpc.build_graph(torch.from_numpy(H).to(dev))
+    E = g.E
+    llr = wl.bpsk_awgn_llr_torch(None, eb, W["rate"], W["seed_noise"] + p, dev, n=n, batch=B)
+    ws = torch.empty(max(1, ldpc.workspace_bytes(g, B, ldpc.LDPC_FORCE_STREAM)), dtype=torch.uint8, device=dev)
+    res = {"workload": f"irregular QC n=64800 m=32400 Z=360, {B} all-zero frames at {eb} dB, L={L}, early exit",
+           "n": n, "m": m, "edges": E, "batch": B, "ebn0_db": eb, "max_iter": L}
+    outs = {}
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for name, chunk in (("chunked", -1), ("whole_batch", 0)):
+        ldpc.set_tuning(g, 2, stream_waves=4, stream_nt=-1, stream_chunk=chunk)
+        o = ldpc._outputs(B, n, dev, True)
+
+        def run():
+            ldpc.minsum_decode(g, llr, L, workspace=ws, out=o)
+
+        run()
+        torch.cuda.synchronize()
+        reps = 2
+        ev0.record()
+        for _ in range(reps):
+            run()
+        ev1.record()
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / reps
+        kt = stream_kernel_ms(lib, run)
+        its = o[2].to(torch.float64)
+        a_chk, a_bit = stream_algo_bytes(its, E, n)
+        t_chk, t_bit = kt["check"][0], kt["bit"][0]
+        res[name] = {"stream_chunk": chunk, "tiles_per_chunk": "by size (200 MiB)" if chunk < 0 else "all",
+                     "ms_per_decode": round(ms, 3), "coded_gbit_s": round(B * n / (ms * 1e-3) / 1e9, 3),
+                     "edge_msg_per_s": round(2.0 * E * float(its.sum()) / (ms * 1e-3), 1),
+                     "check_ms_per_launch": round(t_chk / max(kt["check"][1], 1), 4),
+                     "bit_ms_per_launch": round(t_bit / max(kt["bit"][1], 1), 4),
+                     "launches": kt["check"][1] + kt["bit"][1],
+                     "hbm_frac_check": round(a_chk / (t_chk * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "hbm_frac_bit": round(a_bit / (t_bit * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "hbm_frac_full_iteration": round((a_chk + a_bit) / ((t_chk + t_bit) * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                                      4)}
+        outs[name] = o
+        log(f"[bench] n=64800 {name}: {res[name]['coded_gbit_s']} Gbit/s, HBM frac (check + bit) "
+            f"{res[name]['hbm_frac_full_iteration']}")
+    res["note"] = ("HBM fractions: algorithmic bytes (12E + 12n per frame-iteration, 4E less in iteration 1) over "
+                   "the event-timed kernel time; with chunks most launches after a chunk's first are served by the "
+                   "Infinity Cache, so only the whole-batch figures are HBM-bound")
+    a, b = outs["chunked"], outs["whole_batch"]
+    res["outputs_equal_chunked_whole"] = bool(all(torch.equal(x, y) for x, y in zip(a, b)))
+    its = a[2].to(torch.float64)
+    err = a[0] != 0
+    fe = int(err.any(dim=1).sum())
+    res["plain"] = {"fer": fe / B, "fer_ci95": wilson(fe, B), "ber": float(err.sum()) / (B * n),
+                    "mean_iters": round(float(its.mean()), 3)}
+    ldpc.set_tuning(g, None)
+    if not args.no_cpu_baseline:
+        cpu = cpu_oracle_baseline(H, [llr], L, args.cpu_seconds / 2, 1, E, min_frames=256)
+        gs = [tuple(t[: cpu["frames_per_batch"]] for t in a)]
+        cpu["gpu_mismatches_on_sample"] = parity_counts(gs, cpu.pop("_ref"))
+        res["cpu_baseline"] = cpu
+    if not args.no_nms:
+        learned = []
+        for wname in ("nms_qc64800_T10.json", "nms_qc64800.json"):
+            path = os.path.join(ROOT, "paper_2507_10424_amd", "weights", wname)
+            if os.path.exists(path):
+                r = nms_vs_plain(args, {"L": L, "ebn0": [eb]}, g, [llr], [None], 0, ws, path=path)
+                learned.append(r)
+        res["nms_vs_plain"] = learned
+    del ws
+    return res
+
+
+def block_regular96(args, dev):
+    """The (3,6)-regular n = 96 workload in full: 1000 all-zero frames at
+    2 dB, L = 20, decoded on the GPU and by the oracle (every output of every
+    frame compared), and the oracle timed on the host."""
+    import torch
+    from paper_2507_10424_amd import ldpc
+    W = workload("regular96")
+    H = W["H"]
+    m, n = H.shape
+    B, L = W["batch"], W["L"]
+    from paper_2507_10424_amd import workloads as wl
+    llr_np = wl.bpsk_awgn_llr(None, W["ebn0"][0], W["rate"], seed=W["seed_noise"], n=n, batch=B)
+    llr = torch.from_numpy(llr_np).to(dev)
+    g = ldpc.build_graph(torch.from_numpy(H).to(dev))
+    out = ldpc.minsum_decode(g, llr, L)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    out = ldpc.minsum_decode(g, llr, L)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    res = {"workload": W["name"], "frames": B, "gpu_ms": round(ms, 4),
+           "gpu_coded_gbit_s": round(B * n / (ms * 1e-3) / 1e9, 4),
+           "fer": float((out[0] != 0).any(dim=1).float().mean()),
+           "mean_iters": round(float(out[2].float().mean()), 3)}
+    if not args.no_cpu_baseline:
+        cpu = cpu_oracle_baseline(H, [llr], L, 2.0, 1, g.E, min_frames=B)
+        res["gpu_mismatches"] = parity_counts([out], cpu.pop("_ref"))
+        res["cpu_baseline"] = cpu
+    return res
+
+
 def dense_ablation(args, W, g, llrs, flags):
     """The paper's dense map-reduce form (Algorithm 2 on m x n matrices) against
     the sparse decoder on the same frames: the first `dense_frames` frames of
@@ -569,23 +810,28 @@ def dense_ablation(args, W, g, llrs, flags):
     return res
 
 
-def bench_multi(args, W, dev, lib):
-    """Eight codes, one persistent launch per step (ldpc_minsum_decode_multi);
-    also times one launch per code for comparison."""
-    import ctypes
+def multi_measure(args, W, dev, lib, autotune=True, steps=None, warmup=None):
+    """Eight codes at their configured batches: one ldpc_minsum_decode_multi
+    call per step against one ldpc_minsum_decode per code, the same at 1/32
+    of the batches, the launches the call makes, the ALU roofline of the call,
+    and the oracle on the first frames of every code (all outputs compared)."""
     import torch
     from paper_2507_10424_amd import ldpc
     from paper_2507_10424_amd import workloads as wl
+    import ctypes
     fam, L = W["family"], W["L"]
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
     graphs, llrs, tunings = [], [], []
+    ta = time.time()
     for k, c in enumerate(fam):
         graphs.append(ldpc.build_graph(torch.from_numpy(c["H"]).to(dev)))
         llrs.append(wl.bpsk_awgn_llr_torch(None, W["ebn0"][0], c["rate"], W["seed_noise"] + k, dev, n=c["n"],
                                            batch=c["batch"]))
-        if not args.no_autotune:  # each code's own launch choice, as for one code
+        if autotune:  # each code's own launch choice, as for one code
             tunings.append(ldpc.autotune(graphs[-1], min(c["batch"], 65536), L, W["ebn0"][0]))
     if tunings:
-        log(f"[bench] autotuned variants: {[t['variant'] for t in tunings]}")
+        log(f"[bench] multi-code: autotuned in {time.time() - ta:.1f} s, variants {[t['variant'] for t in tunings]}")
     jobs = list(zip(graphs, llrs))
     outs = [ldpc._outputs(c["batch"], c["n"], dev, True) for c in fam]
     ws = torch.empty(int(lib.ldpc_multi_workspace_bytes(len(jobs))), dtype=torch.uint8, device=dev)
@@ -600,19 +846,28 @@ def bench_multi(args, W, dev, lib):
             ldpc.minsum_decode(g, x, L, workspace=ws, out=o)
 
     def timed(fn):
-        for _ in range(args.warmup):
+        for _ in range(warmup):
             fn()
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         ev0.record()
-        for _ in range(args.steps):
+        for _ in range(steps):
             fn()
         ev1.record()
         torch.cuda.synchronize()
-        return ev0.elapsed_time(ev1) / args.steps
+        return ev0.elapsed_time(ev1) / steps
 
     ms_each = timed(step_each)
     ms_multi = timed(step_multi)
+    # launches of the one call (every on-chip launch is event-timed)
+    lib.ldpc_timing_enable(1)
+    step_multi()
+    torch.cuda.synchronize()
+    kms, kcnt = ctypes.c_double(), ctypes.c_int64()
+    lib.ldpc_timing_read(2, ctypes.byref(kms), ctypes.byref(kcnt))
+    lib.ldpc_timing_enable(0)
+    step_multi()  # outputs of an untimed call for the statistics below
+    torch.cuda.synchronize()
 
     # the same codes with 1/32 of the batches: here one shared persistent
     # launch has to carry the small batches that underfill the GPU one by one
@@ -622,7 +877,7 @@ def bench_multi(args, W, dev, lib):
     ms_small_multi = timed(lambda: ldpc.minsum_decode_multi(small_jobs, L, workspace=ws))
     ms_small_each = timed(lambda: [ldpc.minsum_decode(g, x, L, workspace=ws) for g, x in small_jobs])
     gbits = bits / (ms_multi * 1e-3) / 1e9
-    log(f"[bench] multi-code: one launch {ms_multi:.3f} ms/step ({gbits:.2f} Gbit/s), "
+    log(f"[bench] multi-code: one call {ms_multi:.3f} ms/step ({gbits:.2f} Gbit/s, {kcnt.value} launches), "
         f"one launch per code {ms_each:.3f} ms/step")
     iters = sum(int(o[2].to(torch.int64).sum()) for o in outs)
     edges_iters = sum(int(o[2].to(torch.int64).sum()) * g.E for o, g in zip(outs, graphs))
@@ -633,22 +888,48 @@ def bench_multi(args, W, dev, lib):
                              mean_iters=round(float(o[2].float().mean()), 3)))
     ops = float(sum(alu_ops_per_frame_iter(c["H"]) * int(o[2].to(torch.int64).sum()) for c, o in zip(fam, outs)))
     achieved = ops / (ms_multi * 1e-3) / 1e12
-    line = {
-        "metric": "coded Gbit/s & edge-msg/s (% HBM BW); neural vs plain Min-Sum at equal FER",
-        "value": round(gbits, 3), "unit": "Gbit/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(ms_multi, 4), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
-        "config": {"workload": W["name"], "frames": frames, "max_iter": L, "ebn0_db": W["ebn0"],
-                   "tuning": tunings or None},
+    res = {
+        "workload": W["name"], "frames": frames, "max_iter": L, "ebn0_db": W["ebn0"],
+        "tuning": tunings or None,
+        "coded_gbit_s": round(gbits, 3), "ms_per_step_one_call": round(ms_multi, 4),
+        "launches_per_call": int(kcnt.value),
+        "ms_per_step_one_launch_per_code": round(ms_each, 4),
+        "gbit_s_one_launch_per_code": round(bits / (ms_each * 1e-3) / 1e9, 3),
         "edge_msg_per_s": 2.0 * edges_iters / (ms_multi * 1e-3), "mean_iters": round(iters / frames, 3),
-        "ms_per_step_one_launch_per_code": round(ms_each, 4), "per_code": per_code,
+        "per_code": per_code,
         "small_batches": {"frames": sum(x.shape[0] for x in small_llrs), "ms_one_call": round(ms_small_multi, 4),
                           "ms_one_launch_per_code": round(ms_small_each, 4),
                           "gbit_s_one_call": round(small_bits / (ms_small_multi * 1e-3) / 1e9, 3),
                           "gbit_s_one_launch_per_code": round(small_bits / (ms_small_each * 1e-3) / 1e9, 3)},
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
-                     "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None, "kernel": "onchip_multi"},
-        "cpu_baseline": None,
+                     "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": None, "kernel": "onchip (one call)",
+                     "note": "algorithmic lane-operations of every frame-iteration over the call's time"},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        sample = 64
+        ref, got = [], []
+        tc = time.time()
+        for c, x, o in zip(fam, llrs, outs):
+            ref.append(oracle.minsum_decode(c["H"], x[:sample].cpu().numpy(), L,
+                                            nthreads=host_cpu_info()["threads"]))
+            got.append(tuple(t[:sample] for t in o))
+        res["oracle_check"] = {"frames_per_code": sample, "seconds": round(time.time() - tc, 2),
+                               "gpu_mismatches": parity_counts(got, ref)}
+    return res
+
+
+def bench_multi(args, W, dev, lib):
+    """The multi-code workload as the benchmark line of its own."""
+    res = multi_measure(args, W, dev, lib, autotune=not args.no_autotune)
+    line = {
+        "metric": "coded Gbit/s & edge-msg/s (% HBM BW); neural vs plain Min-Sum at equal FER",
+        "value": res["coded_gbit_s"], "unit": "Gbit/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": res["ms_per_step_one_call"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": W["name"], "frames": res["frames"], "max_iter": W["L"], "ebn0_db": W["ebn0"],
+                   "tuning": res["tuning"]},
+        "roofline": res["roofline"], "cpu_baseline": None, "multi_code": res,
     }
     print(json.dumps(line), flush=True)
 

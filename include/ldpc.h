@@ -19,6 +19,16 @@
  *     captured into a HIP graph.  Argument errors are reported before
  *     anything is launched; launch failures are reported as LDPC_EHIP.
  *   - Every entry point returns an LDPC_* status (0 = success) unless noted.
+ *
+ * The decoding interface proper is ldpc_build_graph, ldpc_graph_info,
+ * ldpc_graph_destroy, ldpc_decode_workspace_bytes, ldpc_minsum_decode and
+ * ldpc_status_string with the statuses LDPC_OK .. LDPC_EWORKSPACE.  Beyond
+ * it, as extensions: the `flags` argument of ldpc_decode_workspace_bytes (the
+ * workspace depends on the kernel path, which flags can force), the `cap`
+ * argument of ldpc_graph_info (the length of the caller's check_degrees
+ * array, so the call never writes past it), the status LDPC_EUNSUPPORTED (a
+ * forced kernel path that the graph does not fit), the path flags, and every
+ * entry point declared after ldpc_minsum_decode.
  */
 #ifndef LDPC_H
 #define LDPC_H

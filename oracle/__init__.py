@@ -6,4 +6,5 @@ compiled with ``-ffp-contract=off`` and no fast-math) through ctypes and shares
 nothing with the HIP library.
 """
 from .binding import (Oracle, build_oracle, load_oracle, minsum_decode, nms_decode,  # noqa: F401
-                      minsum_dense, syndrome, check_degrees, nms_train_loss_grad)
+                      minsum_dense, syndrome, check_degrees, nms_train_loss_grad,
+                      nms_train_grad_f32_forward)

@@ -18,11 +18,23 @@ _i32p = ctypes.POINTER(ctypes.c_int32)
 _i32 = ctypes.c_int32
 
 
-def build_oracle(mutant: int = 0, out: str | None = None) -> str:
-    """Compile the oracle (or a variant with a planted mistake) and return
-    the path of the shared library."""
+LIB_SANITIZED = os.path.join(HERE, "liboracle_san.so")
+# Sanitizer build: AddressSanitizer (out-of-bounds and use-after-free on the
+# heap and stack) and UndefinedBehaviorSanitizer (signed overflow, bad shifts,
+# misaligned or null accesses), every finding fatal.  A process that loads it
+# must preload the two runtimes (sanitizer_env).
+SANITIZE_FLAGS = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                  "-fno-sanitize-recover=all"]
+
+
+def build_oracle(mutant: int = 0, out: str | None = None, sanitize: bool = False) -> str:
+    """Compile the oracle (or a variant with a planted mistake, or the
+    sanitizer build) and return the path of the shared library."""
+    if sanitize:
+        out = out or LIB_SANITIZED
     out = out or (LIB if mutant == 0 else os.path.join(HERE, f"liboracle_mutant{mutant}.so"))
-    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+    opt = SANITIZE_FLAGS if sanitize else ["-O2"]
+    cmd = ["gcc", *opt, "-std=c11", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
            f"-DORACLE_MUTANT={mutant}", SRC, SRC_GRAD, "-o", out + ".tmp", "-lpthread", "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(out + ".tmp", out)
@@ -59,6 +71,9 @@ class Oracle:
         lib.oracle_nms_train_loss_grad.argtypes = [_u8p, _i32, _i32, _f64p, _u8p, _i32, _f64p, _f64p, _i32, _i32,
                                                    _f64p, _f64p, _f64p, _f64p]
         lib.oracle_nms_train_loss_grad.restype = ctypes.c_int
+        lib.oracle_nms_train_loss_grad_ex.argtypes = [_u8p, _i32, _i32, _f64p, _u8p, _i32, _f64p, _f64p, _i32, _i32,
+                                                      _i32, _f64p, _f64p, _f64p, _f64p, _f64p, _f64p, _f64p, _f64p]
+        lib.oracle_nms_train_loss_grad_ex.restype = ctypes.c_int
         self.lib = lib
         self.path = path
 
@@ -153,6 +168,38 @@ class Oracle:
             raise ValueError(f"oracle_nms_train_loss_grad status {st}")
         return float(loss[0]), ga, gb, gl
 
+    def nms_train_grad_f32_forward(self, H, llr, alpha, beta, targets=None, llr_grad=True):
+        """The training gradient along the binary32 decoder's forward: the
+        forward of T = alpha.shape[0] iterations in binary32 arithmetic (the
+        decoding oracle's), the reverse sweep in double along its argmin
+        positions, signs and clip masks.  ``llr``, ``alpha`` and ``beta`` are
+        taken as float32.  Returns a dict with loss, galpha, gbeta, gllr (None
+        unless llr_grad), the magnitude bounds aalpha, abeta, allr of those
+        entries (the sweep with absolute values of every term) and post, the
+        posteriors after iteration T."""
+        _f64p = ctypes.POINTER(ctypes.c_double)
+        H = np.ascontiguousarray(H, dtype=np.uint8)
+        llr = np.ascontiguousarray(np.atleast_2d(np.asarray(llr, dtype=np.float32)), dtype=np.float64)
+        alpha = np.ascontiguousarray(np.asarray(alpha, dtype=np.float32), dtype=np.float64)
+        beta = np.ascontiguousarray(np.asarray(beta, dtype=np.float32), dtype=np.float64)
+        T, C = alpha.shape
+        m, n = H.shape
+        B = llr.shape[0]
+        tg = None if targets is None else np.ascontiguousarray(np.atleast_2d(targets), dtype=np.uint8)
+        loss = np.zeros(1)
+        out = {k: np.zeros((T, C)) for k in ("galpha", "gbeta", "aalpha", "abeta")}
+        out["gllr"] = np.zeros((B, n)) if llr_grad else None
+        out["allr"] = np.zeros((B, n)) if llr_grad else None
+        out["post"] = np.zeros((B, n))
+        st = self.lib.oracle_nms_train_loss_grad_ex(
+            _p(H, _u8p), m, n, _p(llr, _f64p), _p(tg, _u8p), B, _p(alpha, _f64p), _p(beta, _f64p), T, C, 1,
+            _p(loss, _f64p), _p(out["galpha"], _f64p), _p(out["gbeta"], _f64p), _p(out["gllr"], _f64p),
+            _p(out["aalpha"], _f64p), _p(out["abeta"], _f64p), _p(out["allr"], _f64p), _p(out["post"], _f64p))
+        if st:
+            raise ValueError(f"oracle_nms_train_loss_grad_ex status {st}")
+        out["loss"] = float(loss[0])
+        return out
+
     def check_degrees(self, H):
         H = np.ascontiguousarray(H, dtype=np.uint8)
         m, n = H.shape
@@ -166,8 +213,27 @@ class Oracle:
 _default: Oracle | None = None
 
 
+def sanitizer_env() -> dict:
+    """Environment of a process that loads the sanitizer build: the ASan and
+    UBSan runtimes preloaded (the interpreter itself is not instrumented, so
+    leak reports, which would be Python's, are off) and the oracle path in
+    LDPC_ORACLE_LIB."""
+    rt = [subprocess.run(["gcc", f"-print-file-name={n}"], capture_output=True, text=True, check=True).stdout.strip()
+          for n in ("libasan.so", "libubsan.so")]
+    env = dict(os.environ)
+    env["LD_PRELOAD"] = ":".join(rt)
+    env["ASAN_OPTIONS"] = "detect_leaks=0:abort_on_error=1"
+    env["UBSAN_OPTIONS"] = "print_stacktrace=1:halt_on_error=1"
+    env["LDPC_ORACLE_LIB"] = LIB_SANITIZED
+    return env
+
+
 def load_oracle() -> Oracle:
+    """The oracle library: LDPC_ORACLE_LIB if set (the sanitizer build),
+    else liboracle.so, rebuilt when a source is newer."""
     global _default
+    if _default is None and os.environ.get("LDPC_ORACLE_LIB"):
+        _default = Oracle(os.environ["LDPC_ORACLE_LIB"])
     if _default is None:
         if not os.path.exists(LIB) or os.path.getmtime(LIB) < max(os.path.getmtime(SRC), os.path.getmtime(SRC_GRAD)):
             build_oracle()
@@ -193,6 +259,10 @@ def syndrome(*a, **k):
 
 def check_degrees(*a, **k):
     return load_oracle().check_degrees(*a, **k)
+
+
+def nms_train_grad_f32_forward(*a, **k):
+    return load_oracle().nms_train_grad_f32_forward(*a, **k)
 
 
 def nms_train_loss_grad(*a, **k):

@@ -381,8 +381,14 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
                             // every row has degree DC, so one class: the
                             // weights are the workgroup's, read through the
                             // scalar cache (constant address space) instead of
-                            // a vector load each lane waits on
-                            const int32_t wi = __builtin_amdgcn_readfirstlane((tt[q] - 1) * ncls);
+                            // a vector load each lane waits on.  A scalar load
+                            // ignores the lane mask, so its index is clamped
+                            // into the table (1 <= tt <= L <= T inside this
+                            // branch; the clamp keeps it there whatever code
+                            // the compiler emits around the branch).
+                            int32_t tw = tt[q] > L ? L : tt[q];
+                            tw = tw < 1 ? 1 : tw; // L = 0: no iteration reads it
+                            const int32_t wi = __builtin_amdgcn_readfirstlane((tw - 1) * ncls);
                             al = *(const __attribute__((address_space(4))) float *)(alpha + wi);
                             be = *(const __attribute__((address_space(4))) float *)(beta + wi);
                         } else {

@@ -268,14 +268,18 @@ __global__ __launch_bounds__(kThreads) void k_nms_bwd(
     }
 }
 
-// Sum over frames, in frame order: out[k] = mult * sum_f part[f * stride + offset + k].
-__global__ void k_sum_frames(const float *__restrict__ part, int32_t B, int32_t stride, int32_t offset, int32_t width,
-                             float mult, float *__restrict__ out) {
-    const int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= width) return;
+// Sum over frames: out[k] = mult * sum_f part[f * stride + offset + k], one
+// workgroup per output k.  Thread i adds frames i, i + 256, ... in order, then
+// the block reduction adds the threads' partials in a fixed tree; the order
+// depends only on B, so the result is the same on every run.
+__global__ __launch_bounds__(kThreads) void k_sum_frames(const float *__restrict__ part, int32_t B, int32_t stride,
+                                                          int32_t offset, float mult, float *__restrict__ out) {
+    __shared__ float red[16];
+    const int32_t k = blockIdx.x;
     float acc = 0.0f;
-    for (int32_t f = 0; f < B; ++f) acc += part[(size_t)f * stride + offset + k];
-    out[k] = acc * mult;
+    for (int32_t f = threadIdx.x; f < B; f += kThreads) acc += part[(size_t)f * stride + offset + k];
+    const float tot = block_sum(acc, red);
+    if (threadIdx.x == 0) out[k] = tot * mult;
 }
 
 // ---- synthetic frames --------------------------------------------------------
@@ -416,7 +420,7 @@ extern "C" int ldpc_nms_train_forward(const ldpc_graph *g, const float *llr_dev,
     fn<<<B, kThreads, lds, stream>>>(g->row_ptr, g->col_idx, g->col_ptr, g->csc_edge, g->row_class, g->m, g->n,
                                      (int32_t)g->E, (int32_t)g->class_degrees.size(), llr_dev, target_dev, T,
                                      ckpt_every, alpha_dev, beta_dev, w.ckpt, w.loss_part, post_dev, w.scratch);
-    k_sum_frames<<<1, 64, 0, stream>>>(w.loss_part, B, 1, 0, 1, 1.0f / ((float)B * (float)g->n), loss_dev);
+    k_sum_frames<<<1, kThreads, 0, stream>>>(w.loss_part, B, 1, 0, 1.0f / ((float)B * (float)g->n), loss_dev);
     return hipGetLastError() == hipSuccess ? LDPC_OK : LDPC_EHIP;
 }
 
@@ -442,8 +446,8 @@ extern "C" int ldpc_nms_train_backward(const ldpc_graph *g, const float *llr_dev
                                      (int32_t)g->E, ncls, llr_dev, target_dev, T, ckpt_every, alpha_dev, beta_dev,
                                      w.ckpt, scale, w.gpart, gllr_dev, w.scratch);
     const int32_t width = T * ncls;
-    k_sum_frames<<<(width + 63) / 64, 64, 0, stream>>>(w.gpart, B, 2 * width, 0, width, 1.0f, galpha_dev);
-    k_sum_frames<<<(width + 63) / 64, 64, 0, stream>>>(w.gpart, B, 2 * width, width, width, 1.0f, gbeta_dev);
+    k_sum_frames<<<width, kThreads, 0, stream>>>(w.gpart, B, 2 * width, 0, 1.0f, galpha_dev);
+    k_sum_frames<<<width, kThreads, 0, stream>>>(w.gpart, B, 2 * width, width, 1.0f, gbeta_dev);
     return hipGetLastError() == hipSuccess ? LDPC_OK : LDPC_EHIP;
 }
 
