@@ -147,6 +147,34 @@ int ldpc_minsum_decode(const ldpc_graph *g, const float *llr_dev, int32_t B, int
                        uint8_t *ok_dev, void *ws_dev, size_t ws_bytes, hipStream_t stream);
 
 /*
+ * Largest workspace ldpc_minsum_decode_noalloc can serve from the library's
+ * own device memory: 16 MiB per GPU.  The on-chip path needs about 2 KiB for
+ * any batch; the streaming path needs 256 (2 n + E) bytes per frame rounded
+ * up to tiles of 64 frames, plus 16 bytes per frame.
+ */
+#define LDPC_NOALLOC_SCRATCH_BYTES ((size_t)16 << 20)
+
+/*
+ * ldpc_minsum_decode without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops that
+ * must not call hipMalloc, harnesses that forbid it).  The kernels use a
+ * fixed scratch array that the library holds on every GPU it runs on (its
+ * address is looked up once per device, at the first call on that device);
+ * the call itself allocates nothing.  Inputs, outputs, flags, results and the
+ * other errors are those of ldpc_minsum_decode.  The graph must live on the
+ * current device (else LDPC_EINVAL).  A decode whose workspace
+ * (ldpc_decode_workspace_bytes(g, B, flags)) exceeds
+ * LDPC_NOALLOC_SCRATCH_BYTES returns LDPC_EWORKSPACE and launches nothing.
+ * Every call on one GPU shares that GPU's scratch array, and each call
+ * re-initialises what it needs from it: calls that may overlap on one GPU
+ * (other streams, other host threads) race and must be serialised by the
+ * caller, e.g. by issuing them on one stream.
+ */
+int ldpc_minsum_decode_noalloc(const ldpc_graph *g, const float *llr_dev, int32_t B, int32_t max_iter,
+                               uint32_t flags, uint8_t *bits_dev, float *post_dev, int32_t *iters_dev,
+                               uint8_t *ok_dev, hipStream_t stream);
+
+/*
  * The paper's dense map-reduce form of the same decoder (Algorithm 2, Sec. III),
  * as an ablation of the sparse design: per frame, lambda and eta are full
  * m x n matrices (zero where H(i,j) = 0), each row reduction runs over all n

@@ -1,8 +1,33 @@
 // C-ABI entry points of libldpc: argument checks, workspace sizing and the
 // choice of kernel path.
+#include <mutex>
+
 #include "ldpc_internal.h"
 
+// Device memory of ldpc_minsum_decode_noalloc: the workspace of its kernels.
+// Each GPU the library runs on holds its own copy until the process ends.  In
+// host code `scratch` only names the symbol; its device address comes from
+// hipGetSymbolAddress, once per device (scratch_on).
+static __device__ __align__(256) unsigned char scratch[LDPC_NOALLOC_SCRATCH_BYTES];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {}; // device address of `scratch` per device, null until looked up
+
+// The address of `scratch` on `device`, which must be the current device
+// (looked up on the first call on that device), or null on failure.
+void *scratch_on(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+        g_scratch_ptr[device] = p;
+    }
+    return g_scratch_ptr[device];
+}
 
 int check_common(const ldpc_graph *g, const float *llr, int32_t B, int32_t L, uint8_t *bits, int32_t *iters) {
     if (!g || B < 0 || L < 0) return LDPC_EINVAL;
@@ -56,6 +81,25 @@ extern "C" int ldpc_nms_decode(const ldpc_graph *g, const float *llr_dev, int32_
     if (!alpha_dev || !beta_dev || T < 1 || max_iter > T) return LDPC_EINVAL;
     return decode(g, llr_dev, B, max_iter, flags, alpha_dev, beta_dev, T, bits_dev, post_dev, iters_dev, ok_dev,
                   ws_dev, ws_bytes, stream);
+}
+
+extern "C" int ldpc_minsum_decode_noalloc(const ldpc_graph *g, const float *llr_dev, int32_t B, int32_t max_iter,
+                                          uint32_t flags, uint8_t *bits_dev, float *post_dev, int32_t *iters_dev,
+                                          uint8_t *ok_dev, hipStream_t stream) {
+    int st = check_common(g, llr_dev, B, max_iter, bits_dev, iters_dev);
+    if (st) return st;
+    if ((flags & LDPC_FORCE_STREAM) && (flags & LDPC_FORCE_ONCHIP)) return LDPC_EINVAL;
+    if (flags & ~ldpc::kKnownFlags) return LDPC_EINVAL;
+    if (B == 0) return LDPC_OK;
+    int device = -1;
+    if (hipGetDevice(&device) != hipSuccess) return LDPC_EHIP;
+    if (device != g->device) return LDPC_EINVAL;
+    const size_t need = ldpc_decode_workspace_bytes(g, B, flags);
+    if (need > LDPC_NOALLOC_SCRATCH_BYTES) return LDPC_EWORKSPACE;
+    void *ws = scratch_on(device);
+    if (!ws) return LDPC_EHIP;
+    return decode(g, llr_dev, B, max_iter, flags, nullptr, nullptr, 0, bits_dev, post_dev, iters_dev, ok_dev, ws,
+                  LDPC_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 extern "C" size_t ldpc_dense_workspace_bytes(const ldpc_graph *g, int32_t B) {

@@ -88,6 +88,8 @@ def load_library():
     lib.ldpc_decode_workspace_bytes.restype = ctypes.c_size_t
     lib.ldpc_minsum_decode.argtypes = [_vp, _vp, _i32, _i32, _u32, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t, _vp]
     lib.ldpc_minsum_decode.restype = ctypes.c_int
+    lib.ldpc_minsum_decode_noalloc.argtypes = [_vp, _vp, _i32, _i32, _u32, _vp, _vp, _vp, _vp, _vp]
+    lib.ldpc_minsum_decode_noalloc.restype = ctypes.c_int
     lib.ldpc_dense_workspace_bytes.argtypes = [_vp, _i32]
     lib.ldpc_dense_workspace_bytes.restype = ctypes.c_size_t
     lib.ldpc_minsum_decode_dense.argtypes = [_vp, _vp, _i32, _i32, _u32, _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t,
@@ -226,6 +228,26 @@ def minsum_decode(g: Graph, llr: torch.Tensor, max_iter: int, flags: int = 0, wa
                                     _stream(llr.device))
     if st:
         raise LdpcError(st, "ldpc_minsum_decode")
+    return bits, post, iters, ok
+
+
+NOALLOC_SCRATCH_BYTES = 16 << 20  # LDPC_NOALLOC_SCRATCH_BYTES
+
+
+def minsum_decode_noalloc(g: Graph, llr: torch.Tensor, max_iter: int, flags: int = 0, out=None):
+    """ldpc_minsum_decode_noalloc: the decode with the library's own scratch
+    memory instead of a workspace (decodes needing more than 16 MiB of
+    workspace are refused).  ``out`` = (bits, post or None, iters, ok)
+    preallocated; without it the outputs are allocated here."""
+    llr = _check_llr(g, llr)
+    B = llr.shape[0]
+    bits, post, iters, ok = out if out is not None else _outputs(B, g.n, llr.device, True)
+    lib = load_library()
+    with torch.cuda.device(llr.device):
+        st = lib.ldpc_minsum_decode_noalloc(g.handle, _ptr(llr), B, int(max_iter), int(flags), _ptr(bits),
+                                            _ptr(post), _ptr(iters), _ptr(ok), _stream(llr.device))
+    if st:
+        raise LdpcError(st, "ldpc_minsum_decode_noalloc")
     return bits, post, iters, ok
 
 
