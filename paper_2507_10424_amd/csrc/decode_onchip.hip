@@ -129,6 +129,12 @@ size_t state_bytes(const ldpc_graph &g, int F) {
 
 size_t lds_bytes_for(const ldpc_graph &g, int F) { return state_bytes(g, F) + sizeof(Shared); }
 
+// The bank-conflict-free layout (two frame slots, 8-byte entries): s[n], then
+// the messages from a 256-byte boundary (so that a position's bank class is
+// the position modulo 32), cf.npos entries.
+uint32_t cf_eta_offset(const ldpc_graph &g) { return (uint32_t)align_up(8 * (size_t)g.n, 256); }
+size_t cf_state_bytes(const ldpc_graph &g) { return align_up(cf_eta_offset(g) + 8 * (size_t)g.cf.npos, 16); }
+
 __global__ void k_zero_u32(uint32_t *p) { *p = 0u; }
 
 template <class V> __device__ __forceinline__ V lds_ld(const unsigned char *base, uint32_t off) {
@@ -163,6 +169,14 @@ struct Job {
     int32_t variant;  // index into kVariants
     uint32_t *queue;  // kQueues frame counters (kQueueStride words apart), zero before the launch
     int32_t nq;       // counters in use (queues_for(B))
+    // bank-conflict-free layout (CF variants): tables of the graph, the LDS
+    // byte offset of the messages and their number of positions
+    const uint32_t *cf_edge;
+    const uint32_t *cf_bitpos;
+    const int32_t *cf_slot_bit;
+    const int32_t *cf_row_class;
+    uint32_t cf_eta_off;
+    int32_t cf_npos;
 };
 
 // Decodes all frames of one job with the workgroup (see the file comment).
@@ -173,8 +187,14 @@ struct Job {
 // this workgroup are done.
 // NMS: the learned check update (J.alpha, J.beta non-null); plain Min-Sum
 // instantiations carry no trace of it.
-template <int DC, bool RX, int DV, bool CX, int RPT, int CPT, int F, bool NMS>
+// CF: the bank-conflict-free layout of the graph (layout.hip): rows and bits
+// in the thread slots its tables give, and every edge's message at a
+// position of its own that both passes read from LDS (so the previous
+// messages are not kept in registers); needs exact degrees and its
+// geometry (two rows, four bits per thread).
+template <int DC, bool RX, int DV, bool CX, int RPT, int CPT, int F, bool NMS, bool CF>
 __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t early, unsigned char *lds) {
+    static_assert(!CF || (RX && CX && RPT == 2 && CPT == 4 && F == 2), "layout geometry");
     typedef typename Vec<F>::type V;
     constexpr uint32_t kEnt = sizeof(V); // bytes of one LDS entry (F floats)
     // read all s (messages) of the check (bit) pass up front when that takes
@@ -206,7 +226,7 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
     const int32_t ncls = J.ncls;
     uint32_t *__restrict__ queue = J.queue;
     const int32_t nq = J.nq;
-    const uint32_t eta0 = kEnt * (uint32_t)n; // byte offset of eta
+    const uint32_t eta0 = CF ? J.cf_eta_off : kEnt * (uint32_t)n; // byte offset of eta
     Shared *sh = reinterpret_cast<Shared *>(lds + sh_off);
     const int tid = threadIdx.x;
     const int nt = blockDim.x;
@@ -217,6 +237,18 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
         const int32_t i = tid + r * nt;
+        if constexpr (CF) {
+            // every slot has a table entry (slots past m: bit 0, the spare position)
+            deg[r] = DC;
+            rcls[r] = NMS ? J.cf_row_class[i] : 0;
+#pragma unroll
+            for (int k = 0; k < DC; ++k) {
+                const uint32_t w = J.cf_edge[(size_t)i * DC + k];
+                sa[r][k] = kEnt * (w & 0xffffu);
+                ea[r][k] = eta0 + kEnt * (w >> 16);
+            }
+            continue;
+        }
         const int32_t e0 = i < m ? row_ptr[i] : 0;
         const int32_t d = i < m ? row_ptr[i + 1] - e0 : 0;
         deg[r] = d;
@@ -235,6 +267,20 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
         const int32_t j = tid + c * nt;
         const int32_t k0 = j < n ? col_ptr[j] : E;
         ckd[c] = (uint32_t)k0 | ((uint32_t)(j < n ? col_ptr[j + 1] - k0 : 0) << 16);
+    }
+    // Own bit slots p = tid + c nt (LDS s at kEnt p): the bit index they hold
+    // (frame I/O) and, in the layout, their messages' LDS addresses.
+    int32_t gj[CPT];
+    uint32_t ba[CF ? CPT : 1][CF ? DV : 1];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+        const int32_t p = tid + c * nt;
+        gj[c] = CF ? (p < n ? J.cf_slot_bit[p] : 0) : p;
+        if constexpr (CF) {
+#pragma unroll
+            for (int u = 0; u < DV; ++u)
+                ba[c][u] = eta0 + kEnt * (p < n ? J.cf_bitpos[(size_t)p * DV + u] : (uint32_t)(J.cf_npos - 1));
+        }
     }
 
     // ---- slots --------------------------------------------------------------
@@ -292,7 +338,7 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
 #pragma unroll
             for (int q = 0; q < F; ++q) {
                 const int32_t nx = __builtin_amdgcn_readfirstlane(sh->next[q][0]);
-                rnx[c][q] = llr[(size_t)(nx < B ? nx : 0) * n + (j < n ? j : 0)];
+                rnx[c][q] = llr[(size_t)(nx < B ? nx : 0) * n + (j < n ? gj[c] : 0)];
             }
         }
     }
@@ -300,13 +346,17 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
     for (int r = 0; r < RPT; ++r)
 #pragma unroll
         for (int k = 0; k < DC; ++k) eprev[r][k] = vzero<V>();
+    if constexpr (CF) { // every message starts at 0 (first iteration of every slot)
+        for (int32_t e = tid; e < J.cf_npos; e += nt) lds_st<V>(lds, eta0 + kEnt * (uint32_t)e, vzero<V>());
+    }
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
         const int32_t j = tid + c * nt;
         rc[c] = vzero<V>();
         if (j < n) {
 #pragma unroll
-            for (int q = 0; q < F; ++q) rc[c][q] = fr[q] < B ? llr[(size_t)fr[q] * n + j] + 0.0f : 0.0f; // -0 -> +0
+            for (int q = 0; q < F; ++q)
+                rc[c][q] = fr[q] < B ? llr[(size_t)fr[q] * n + gj[c]] + 0.0f : 0.0f; // -0 -> +0
             lds_st<V>(lds, kEnt * (uint32_t)j, rc[c]);
         }
     }
@@ -332,21 +382,30 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
         // before the first row's messages are written (the compiler cannot
         // move a read of s above an LDS write it cannot tell apart from it),
         // so the reads of later rows overlap the work of earlier ones.
-        V svp[RPT][DC];
+        // In the layout (CF), each edge's previous message is read from its
+        // LDS position as well, in the same batch.
+        V svp[RPT][DC], pvp[CF ? RPT : 1][CF ? DC : 1];
         if constexpr (kPrefetchS) {
 #pragma unroll
             for (int r = 0; r < RPT; ++r)
 #pragma unroll
-                for (int k = 0; k < DC; ++k) svp[r][k] = lds_ld<V>(lds, sa[r][k]);
+                for (int k = 0; k < DC; ++k) {
+                    svp[r][k] = lds_ld<V>(lds, sa[r][k]);
+                    if constexpr (CF) pvp[r][k] = lds_ld<V>(lds, ea[r][k]);
+                }
         }
         uint32_t umask = 0;
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
             const int32_t d = RX ? DC : deg[r];
             const bool rowv = RX ? (tid + r * nt < m) : deg[r] > 0; // RX: recomputed, saves a register
-            V sv[DC];
+            V sv[DC], pv_[DC], msg[DC];
 #pragma unroll
-            for (int k = 0; k < DC; ++k) sv[k] = kPrefetchS ? svp[r][k] : lds_ld<V>(lds, sa[r][k]);
+            for (int k = 0; k < DC; ++k) {
+                sv[k] = kPrefetchS ? svp[r][k] : lds_ld<V>(lds, sa[r][k]);
+                if constexpr (CF) pv_[k] = kPrefetchS ? pvp[r][k] : lds_ld<V>(lds, ea[r][k]);
+                else pv_[k] = eprev[r][k];
+            }
 #pragma unroll
             for (int q = 0; q < F; ++q) {
                 // RX: every edge of a real row is valid; rows past m compute
@@ -357,7 +416,7 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
 #pragma unroll
                 for (int k = 0; k < DC; ++k) {
                     const bool valid = RX || k < d;
-                    const float x = sv[k][q] - eprev[r][k][q];
+                    const float x = sv[k][q] - pv_[k][q];
                     xb[k] = __float_as_uint(x);
                     a[k] = valid ? fabsf(x) : __builtin_inff();
                 }
@@ -407,18 +466,20 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
                     asm("" : "+v"(b0s), "+v"(b1s));
 #pragma unroll
                     for (int k = 0; k < DC; ++k)
-                        eprev[r][k][q] = __uint_as_float(((a[k] == mn0) ? b1s : b0s) ^ (xb[k] & 0x80000000u));
+                        msg[k][q] = __uint_as_float(((a[k] == mn0) ? b1s : b0s) ^ (xb[k] & 0x80000000u));
                 } else {
                     // two instructions per edge (edge_message); a zero message's
                     // sign changes no s (r is never -0, and s = sum + r)
                     const uint32_t K = row_word(mn0, mn1, par);
 #pragma unroll
-                    for (int k = 0; k < DC; ++k) eprev[r][k][q] = edge_message(__uint_as_float(xb[k]), mn1, K);
+                    for (int k = 0; k < DC; ++k) msg[k][q] = edge_message(__uint_as_float(xb[k]), mn1, K);
                 }
             }
 #pragma unroll
-            for (int k = 0; k < DC; ++k)
-                if (RX || k < d) lds_st<V>(lds, ea[r][k], eprev[r][k]); // rows past m write the padding slot
+            for (int k = 0; k < DC; ++k) {
+                if constexpr (!CF) eprev[r][k] = msg[k];
+                if (RX || k < d) lds_st<V>(lds, ea[r][k], msg[k]); // rows past m write the padding slot
+            }
         }
 
         // ---- per-slot syndrome over the workgroup ------------------------------
@@ -447,7 +508,7 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
 #pragma unroll
                     for (int c = 0; c < CPT; ++c) {
                         const int32_t j = tid + c * nt;
-                        rnx[c][q] = llr[(size_t)(nx < B ? nx : 0) * n + (j < n ? j : 0)];
+                        rnx[c][q] = llr[(size_t)(nx < B ? nx : 0) * n + (j < n ? gj[c] : 0)];
                     }
                 }
                 pend = 0;
@@ -470,8 +531,8 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
                 const int32_t j = tid + c * nt;
                 if (j < n) {
                     const float v = lds_ld<V>(lds, kEnt * (uint32_t)j)[q];
-                    if (post) post[(size_t)f * n + j] = v;
-                    bits[(size_t)f * n + j] = v < 0.0f ? 1 : 0;
+                    if (post) post[(size_t)f * n + gj[c]] = v;
+                    bits[(size_t)f * n + gj[c]] = v < 0.0f ? 1 : 0;
                 }
             }
             if (tid == 0) {
@@ -488,10 +549,12 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
             }
             fr[q] = nf;
             gen[q] += 1;
+            if constexpr (!CF) { // (CF: the bit pass zeroes the slot's messages in LDS)
 #pragma unroll
-            for (int r = 0; r < RPT; ++r)
+                for (int r = 0; r < RPT; ++r)
 #pragma unroll
-                for (int k = 0; k < DC; ++k) eprev[r][k][q] = 0.0f;
+                    for (int k = 0; k < DC; ++k) eprev[r][k][q] = 0.0f;
+            }
         }
 
         fin = __builtin_amdgcn_readfirstlane(fin);
@@ -509,6 +572,7 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
         // As in the check pass: when the registers allow, the messages of all
         // own bits are read before the first s is written.  Bits past n read
         // a valid slot (bit 0's, or the padding slot) and write nothing.
+        // CF: each message at its own position (ba), in ascending check order.
         V evp[CPT][DV];
         if constexpr (kPrefetchEta) {
 #pragma unroll
@@ -519,7 +583,8 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
                 const int32_t dv = CX ? DV : (int32_t)(ckd[c] >> 16);
 #pragma unroll
                 for (int k = 0; k < DV; ++k)
-                    evp[c][k] = lds_ld<V>(lds, base + kEnt * (uint32_t)(CX || k < dv ? k : 0));
+                    evp[c][k] = CF ? lds_ld<V>(lds, ba[CF ? c : 0][CF ? k : 0])
+                                   : lds_ld<V>(lds, base + kEnt * (uint32_t)(CX || k < dv ? k : 0));
             }
         }
 #pragma unroll
@@ -533,22 +598,40 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
                 V ev[DV];
 #pragma unroll
                 for (int k = 0; k < DV; ++k)
-                    ev[k] = kPrefetchEta ? evp[c][k] : lds_ld<V>(lds, base + kEnt * (uint32_t)(CX || k < dv ? k : 0));
+                    ev[k] = kPrefetchEta ? evp[c][k]
+                            : CF         ? lds_ld<V>(lds, ba[CF ? c : 0][CF ? k : 0])
+                                         : lds_ld<V>(lds, base + kEnt * (uint32_t)(CX || k < dv ? k : 0));
                 V acc = (CX || 0 < dv) ? ev[0] : vzero<V>();
 #pragma unroll
                 for (int k = 1; k < DV; ++k)
                     acc = acc + ((CX || k < dv) ? ev[k] : vzero<V>()); // +0 adds change no s
-                V sn = acc + rc[c];
+                lds_st<V>(lds, kEnt * (uint32_t)j, acc + rc[c]);
+            }
+        }
+        // Slots refilled this round start their new frame from s = r: their
+        // entries are overwritten (the same thread wrote them just above).  A
+        // refill happens in few rounds, so this is a branch on the uniform
+        // refill mask rather than a select on every bit of every round.
+        if (fin) {
 #pragma unroll
-                for (int q = 0; q < F; ++q) {
-                    if ((fin >> q) & 1u) {
-                        const float v = kAheadLLR ? rnx[c][q] + 0.0f // -0 -> +0
-                                                  : (fr[q] < B ? llr[(size_t)fr[q] * n + j] + 0.0f : 0.0f);
-                        rc[c][q] = v;
-                        sn[q] = v;
+            for (int c = 0; c < CPT; ++c) {
+                const int32_t j = tid + c * nt;
+                if (j < n) {
+#pragma unroll
+                    for (int q = 0; q < F; ++q) {
+                        if ((fin >> q) & 1u) {
+                            const float v = kAheadLLR ? rnx[c][q] + 0.0f // -0 -> +0
+                                                      : (fr[q] < B ? llr[(size_t)fr[q] * n + gj[c]] + 0.0f : 0.0f);
+                            rc[c][q] = v;
+                            lds_st<float>(lds, kEnt * (uint32_t)j + 4u * (uint32_t)q, v);
+                            if constexpr (CF) { // the new frame's first iteration reads 0 messages
+#pragma unroll
+                                for (int u = 0; u < DV; ++u)
+                                    lds_st<float>(lds, ba[CF ? c : 0][CF ? u : 0] + 4u * (uint32_t)q, 0.0f);
+                            }
+                        }
                     }
                 }
-                lds_st<V>(lds, kEnt * (uint32_t)j, sn);
             }
         }
         __syncthreads();
@@ -564,7 +647,8 @@ struct Variant {
     bool cx;
     int rpt;
     int cpt;
-    int f; // frame slots per workgroup
+    int f;   // frame slots per workgroup
+    bool cf; // the graph's bank-conflict-free layout
 };
 
 // Exact-degree variants for the regular codes in use first, then masked ones,
@@ -578,14 +662,14 @@ constexpr Variant kVariants[] = {
     {12, true, 8, false, 1, 4, 2}, {16, true, 8, false, 1, 8, 2}, {8, false, 8, false, 2, 4, 2},
     {16, false, 16, false, 1, 8, 2}, {6, true, 3, true, 1, 4, 2}, {6, true, 3, true, 2, 4, 4},
     {6, true, 3, true, 1, 4, 4},     {6, true, 6, false, 2, 4, 2},  {9, true, 6, false, 2, 8, 2},
-    {12, true, 6, false, 1, 4, 2},   {16, true, 6, false, 1, 8, 2},
+    {12, true, 6, false, 1, 4, 2},   {16, true, 6, false, 1, 8, 2}, {6, true, 3, true, 2, 4, 2, true},
 };
 constexpr int kNumVariants = (int)(sizeof(kVariants) / sizeof(kVariants[0]));
 
 template <int V, bool NMS>
 __device__ __forceinline__ void run_v(const Job &J, int32_t L, int32_t early, unsigned char *lds) {
     constexpr Variant v = kVariants[V];
-    run_onchip<v.dc, v.rx, v.dv, v.cx, v.rpt, v.cpt, v.f, NMS>(J, L, early, lds);
+    run_onchip<v.dc, v.rx, v.dv, v.cx, v.rpt, v.cpt, v.f, NMS, v.cf>(J, L, early, lds);
 }
 
 
@@ -615,9 +699,12 @@ __global__ __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(W >
 // The widest masked variant is left out of the multi-code kernel: the
 // register demand of a kernel is that of its largest variant, and that one
 // alone would push every variant of the launch into spills.  Jobs that need
-// it get a launch of their own.
+// it get a launch of their own.  So is the bank-conflict-free layout: its
+// tables are built for the graph's own thread count, and the shared launch
+// runs the largest thread count of its jobs.
 constexpr int kWideVariant = 6;
-static_assert(kNumVariants == 14, "k_onchip_multi dispatches variants 0-5 and 7-13");
+constexpr bool shared_launch_ok(int v) { return v != kWideVariant && !kVariants[v].cf; }
+static_assert(kNumVariants == 15, "k_onchip_multi dispatches variants 0-5 and 7-13");
 
 __global__ __launch_bounds__(kMaxThreads) void k_onchip_multi(const JobTable jt, int32_t L, int32_t early) {
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
@@ -636,7 +723,7 @@ __global__ __launch_bounds__(kMaxThreads) void k_onchip_multi(const JobTable jt,
         case 11: run_v<11, false>(jt.job[c], L, early, lds); break;
         case 12: run_v<12, false>(jt.job[c], L, early, lds); break;
         case 13: run_v<13, false>(jt.job[c], L, early, lds); break;
-        default: break; // the host never places kWideVariant here
+        default: break; // the host places no variant here that fails shared_launch_ok
         }
         __syncthreads();
     }
@@ -647,7 +734,7 @@ using KernelFn = void (*)(const JobTable, int32_t, int32_t);
 #define LDPC_ONCHIP_ROW(W, N)                                                                                      \
     {&k_onchip<0, W, N>, &k_onchip<1, W, N>, &k_onchip<2, W, N>, &k_onchip<3, W, N>, &k_onchip<4, W, N>,         \
      &k_onchip<5, W, N>, &k_onchip<6, W, N>, &k_onchip<7, W, N>, &k_onchip<8, W, N>, &k_onchip<9, W, N>,         \
-     &k_onchip<10, W, N>, &k_onchip<11, W, N>, &k_onchip<12, W, N>, &k_onchip<13, W, N>}
+     &k_onchip<10, W, N>, &k_onchip<11, W, N>, &k_onchip<12, W, N>, &k_onchip<13, W, N>, &k_onchip<14, W, N>}
 const KernelFn kKernels[2][2][kNumVariants] = {{LDPC_ONCHIP_ROW(0, false), LDPC_ONCHIP_ROW(4, false)},
                                                {LDPC_ONCHIP_ROW(0, true), LDPC_ONCHIP_ROW(4, true)}};
 #undef LDPC_ONCHIP_ROW
@@ -665,15 +752,23 @@ bool variant_ok(const ldpc_graph &g, int k) {
     const Variant &v = kVariants[k];
     const bool rows_ok = v.rx ? (g.dc_min == v.dc && g.dc_max == v.dc) : g.dc_max <= v.dc;
     const bool cols_ok = v.cx ? (g.dv_min == v.dv && g.dv_max == v.dv) : g.dv_max <= v.dv;
-    return rows_ok && cols_ok && threads_for(g, v) <= kMaxThreads && g.edge_tab != nullptr &&
-           lds_bytes_for(g, v.f) + 1024 <= (size_t)g.lds_max;
+    // the layout's tables are for exact degrees and their own thread count
+    const bool cf_ok = !v.cf || (g.cf.edge != nullptr && g.dc_min == v.dc && g.dv_min == v.dv &&
+                                 threads_for(g, v) == g.cf.nt);
+    const size_t state = v.cf ? cf_state_bytes(g) : state_bytes(g, v.f);
+    return rows_ok && cols_ok && cf_ok && threads_for(g, v) <= kMaxThreads && g.edge_tab != nullptr &&
+           state + sizeof(Shared) + 1024 <= (size_t)g.lds_max;
 }
 
-size_t lds_of(const ldpc_graph &g, int variant) { return lds_bytes_for(g, kVariants[variant].f); }
+size_t state_of(const ldpc_graph &g, int variant) {
+    return kVariants[variant].cf ? cf_state_bytes(g) : state_bytes(g, kVariants[variant].f);
+}
+size_t lds_of(const ldpc_graph &g, int variant) { return state_of(g, variant) + sizeof(Shared); }
 
-// Default preference when nothing is tuned: exact degrees first, a column
-// mask of 6 before one of 8, two frame slots before four.
-constexpr int kPickOrder[] = {0, 7, 10, 1, 11, 2, 12, 3, 13, 4, 5, 6, 8, 9};
+// Default preference when nothing is tuned: the bank-conflict-free layout,
+// then exact degrees, a column mask of 6 before one of 8, two frame slots
+// before four.
+constexpr int kPickOrder[] = {14, 0, 7, 10, 1, 11, 2, 12, 3, 13, 4, 5, 6, 8, 9};
 static_assert(sizeof(kPickOrder) / sizeof(kPickOrder[0]) == kNumVariants, "every variant has a place");
 
 // The tuned variant if one is set and valid, else the first that fits.
@@ -694,7 +789,13 @@ Job make_job(const ldpc_graph &g, int variant, const float *llr, int32_t B, uint
     J.m = g.m;
     J.n = g.n;
     J.E = (int32_t)g.E;
-    J.sh_off = (uint32_t)state_bytes(g, kVariants[variant].f);
+    J.sh_off = (uint32_t)state_of(g, variant);
+    J.cf_edge = g.cf.edge;
+    J.cf_bitpos = g.cf.bitpos;
+    J.cf_slot_bit = g.cf.slot_bit;
+    J.cf_row_class = g.cf.row_class;
+    J.cf_eta_off = cf_eta_offset(g);
+    J.cf_npos = g.cf.npos;
     J.llr = llr;
     J.B = B;
     J.bits = bits;
@@ -820,16 +921,16 @@ int onchip_decode_multi(const ldpc_job *jobs, int32_t njobs, int32_t L, uint32_t
         if (jb.B == 0) continue;
         const int v_own = pick(g);
         int v = v_own;
-        if (v == kWideVariant) // another variant that fits keeps the job eligible for the shared launch
-            for (int c = 0; c < kNumVariants; ++c)
-                if (c != kWideVariant && variant_ok(g, c)) {
+        if (!shared_launch_ok(v)) // another variant that fits keeps the job eligible for the shared launch
+            for (int c : kPickOrder)
+                if (shared_launch_ok(c) && variant_ok(g, c)) {
                     v = c;
                     break;
                 }
         const KernelFn fn = kKernels[0][(g.tuning.set && g.tuning.waves_per_simd == 4) ? 1 : 0][v_own];
         const int t_own = threads_for(g, kVariants[v_own]);
         const size_t l_own = lds_of(g, v_own);
-        bool alone = v == kWideVariant;
+        bool alone = !shared_launch_ok(v);
         if (!alone) {
             int per_cu = 0;
             if (hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)l_own) !=

@@ -163,6 +163,13 @@ void free_graph_arrays(ldpc_graph *g) {
     (void)hipFree(g->edge_pos);
     (void)hipFree(g->edge_tab);
     (void)hipFree(g->dense_h);
+    (void)hipFree(g->cf.edge);
+    (void)hipFree(g->cf.bitpos);
+    (void)hipFree(g->cf.slot_bit);
+    (void)hipFree(g->cf.row_class);
+    g->cf.edge = g->cf.bitpos = nullptr;
+    g->cf.slot_bit = g->cf.row_class = nullptr;
+    g->cf.nt = g->cf.npos = 0;
     g->row_ptr = g->col_idx = g->col_ptr = g->csc_edge = g->row_class = g->edge_pos = nullptr;
     g->edge_tab = nullptr;
     g->dense_h = nullptr;
@@ -290,6 +297,32 @@ int build(const uint8_t *H, int32_t m, int32_t n, hipStream_t s, ldpc_graph *g) 
             if (E > 0 && hipMemcpy(g->edge_tab, tab.data(), sizeof(uint32_t) * E, hipMemcpyHostToDevice) != hipSuccess) {
                 fail(LDPC_EHIP);
                 break;
+            }
+            // the bank-conflict-free layout, for one row and one column degree
+            ldpc::OnchipLayout lay;
+            if (E > 0 && g->dc_min == g->dc_max && g->dv_min == g->dv_max &&
+                ldpc::onchip_cf_layout(h_rowptr, h_bit, h_class, m, n, &lay)) {
+                const size_t S = (size_t)ldpc::OnchipLayout::kRpt * lay.nt;
+                if (dalloc(&g->cf.edge, lay.edge.size()) != hipSuccess ||
+                    dalloc(&g->cf.bitpos, lay.bitpos.size()) != hipSuccess ||
+                    dalloc(&g->cf.slot_bit, lay.slot_bit.size()) != hipSuccess ||
+                    dalloc(&g->cf.row_class, S) != hipSuccess) {
+                    fail(LDPC_ENOMEM);
+                    break;
+                }
+                if (hipMemcpy(g->cf.edge, lay.edge.data(), sizeof(uint32_t) * lay.edge.size(),
+                              hipMemcpyHostToDevice) != hipSuccess ||
+                    hipMemcpy(g->cf.bitpos, lay.bitpos.data(), sizeof(uint32_t) * lay.bitpos.size(),
+                              hipMemcpyHostToDevice) != hipSuccess ||
+                    hipMemcpy(g->cf.slot_bit, lay.slot_bit.data(), sizeof(int32_t) * lay.slot_bit.size(),
+                              hipMemcpyHostToDevice) != hipSuccess ||
+                    hipMemcpy(g->cf.row_class, lay.row_class.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice) !=
+                        hipSuccess) {
+                    fail(LDPC_EHIP);
+                    break;
+                }
+                g->cf.nt = lay.nt;
+                g->cf.npos = lay.npos;
             }
         }
     } while (false);

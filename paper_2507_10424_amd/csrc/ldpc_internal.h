@@ -32,6 +32,15 @@ struct ldpc_graph {
     // On-chip path tables (built when n and E are below 2^16): per CSR edge
     // the bit index in the low 16 bits and the CSC slot in the high 16 bits.
     uint32_t *edge_tab = nullptr; // E, or null
+    // Bank-conflict-free on-chip layout (OnchipLayout), built for graphs with
+    // one row degree and one column degree that fit it; null otherwise.
+    struct {
+        uint32_t *edge = nullptr;     // [row slot][k]: bit slot | message position << 16
+        uint32_t *bitpos = nullptr;   // [bit slot][u]: message position
+        int32_t *slot_bit = nullptr;  // [bit slot]: bit index
+        int32_t *row_class = nullptr; // [row slot]: degree class
+        int32_t nt = 0, npos = 0;     // threads of its geometry, message positions
+    } cf;
     // Device copy of the dense m x n H (0/1 bytes) for the dense map-reduce
     // decoder, kept when m * n <= kDenseMaxBytes; null otherwise.
     uint8_t *dense_h = nullptr;
@@ -76,6 +85,23 @@ size_t onchip_workspace_bytes(const ldpc_graph &g, int32_t B);
 int onchip_decode(const ldpc_graph &g, const float *llr, int32_t B, int32_t L, uint32_t flags,
                   const float *alpha, const float *beta, int32_t T, uint8_t *bits, float *post,
                   int32_t *iters, uint8_t *ok, void *ws, size_t ws_bytes, hipStream_t stream);
+
+// Bank-conflict-free on-chip layout (layout.hip) for a geometry of kRpt
+// rows and kCpt bits per thread: check row slot s = r nt + t and bit slot
+// p = c nt + t hold the row and bit given by the tables (a bit stays in its
+// 64-slot block, slots n and up are empty).
+struct OnchipLayout {
+    static constexpr int kRpt = 2, kCpt = 4;
+    int32_t nt = 0;    // threads
+    int32_t dc = 0, dv = 0; // largest row / column degree
+    int32_t npos = 0;  // message positions (the last one for rows past m)
+    std::vector<uint32_t> edge;      // [row slot][k]: bit slot | message position << 16
+    std::vector<uint32_t> bitpos;    // [bit slot][u]: message position of the bit's u-th check (ascending)
+    std::vector<int32_t> slot_bit;   // [bit slot < n]: the bit it holds
+    std::vector<int32_t> row_class;  // [slot]: degree class of the row (0 past m)
+};
+bool onchip_cf_layout(const std::vector<int32_t> &rowptr, const std::vector<int32_t> &col,
+                      const std::vector<int32_t> &row_class, int32_t m, int32_t n, OnchipLayout *out);
 
 // Several graphs in one on-chip launch.
 size_t onchip_multi_workspace_bytes(int32_t njobs);
