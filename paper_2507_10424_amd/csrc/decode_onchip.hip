@@ -207,8 +207,9 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
     // exact (the masked-column variants are the ones near the 128-register
     // budget of four waves per SIMD, which the 8 would push into spills);
     // the learned update only with exact row degrees, where its weights sit
-    // in scalar registers and leave room for the 8
-    constexpr bool kAheadLLR = CPT * F <= 8 && CX && (!NMS || RX);
+    // in scalar registers and leave room for the 8, and not in the
+    // conflict-free layout, whose bit-side message addresses take them
+    constexpr bool kAheadLLR = CPT * F <= 8 && CX && (!NMS || (RX && !CF));
     const int32_t *__restrict__ row_ptr = J.row_ptr;
     const uint32_t *__restrict__ edge_tab = J.edge_tab;
     const int32_t *__restrict__ col_ptr = J.col_ptr;
@@ -394,7 +395,11 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
                     if constexpr (CF) pvp[r][k] = lds_ld<V>(lds, ea[r][k]);
                 }
         }
-        uint32_t umask = 0;
+        // per slot, the OR of the syndrome words of the own rows: its sign bit
+        // says that one of them is unsatisfied
+        uint32_t usyn[F];
+#pragma unroll
+        for (int q = 0; q < F; ++q) usyn[q] = 0u;
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
             const int32_t d = RX ? DC : deg[r];
@@ -430,8 +435,10 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
                     sb[k] = valid ? __float_as_uint(sv[k][q]) : 0u;
                 }
                 uint32_t par = xor_all<DC>(pv), syn = xor_all<DC>(sb);
-                if (RX && !rowv) syn = 0u;
-                umask |= (syn >> 31) << q;
+                // RX: a row past m reads bit 0's s on all DC edges, so with DC
+                // even its syndrome is 0 without a mask
+                if (RX && (DC % 2) == 1 && !rowv) syn = 0u;
+                usyn[q] |= syn;
                 if constexpr (NMS) {
                     uint32_t b0 = __float_as_uint(mn0), b1 = __float_as_uint(mn1);
                     if (tt[q] <= L && rowv) {
@@ -486,7 +493,7 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
         const int p = round & 1;
         uint32_t wm = 0;
 #pragma unroll
-        for (int q = 0; q < F; ++q) wm |= (__ballot((umask >> q) & 1u) != 0ull ? 1u : 0u) << q;
+        for (int q = 0; q < F; ++q) wm |= (__ballot((int32_t)usyn[q] < 0) != 0ull ? 1u : 0u) << q;
         if ((tid & 63) == 0 && wm) atomicOr(&sh->red[p], wm);
         __syncthreads();
         const uint32_t U = __builtin_amdgcn_readfirstlane(sh->red[p]);

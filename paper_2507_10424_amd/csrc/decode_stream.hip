@@ -358,13 +358,25 @@ __global__ __launch_bounds__(512) void k_bit(const int32_t *__restrict__ col_ptr
         const int32_t col = col0 + c < n ? col0 + c : col0;
         rv[c] = r[((size_t)tile * n + col) * kTile + lane];
     }
+    // Only a column's own messages are loaded: the bounds are uniform across
+    // the wavefront, so each load sits behind a scalar branch (a column of
+    // 2 or 3 checks issues 2 or 3 loads, not 8).
 #pragma unroll
     for (int c = 0; c < CPW; ++c) {
-        const bool any = k1[c] > k0[c];
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
-            ev[c][u] = any ? ld_msg<NT>(&et[(size_t)(k0[c] + u < k1[c] ? idx0[c][u] : idx0[c][0]) * kTile]) : 0.0f;
+        for (int u = 0; u < 8; ++u) {
+            ev[c][u] = 0.0f;
+            if (k0[c] + u < k1[c]) ev[c][u] = ld_msg<NT>(&et[(size_t)idx0[c][u] * kTile]);
+        }
     }
+    // The adds below are under the same conditions as the loads; the compiler
+    // would merge them into the load branches, where the first add waits for
+    // its load before the other loads are issued.  Passing every loaded value
+    // through an empty asm once all loads are issued keeps the adds after it.
+#pragma unroll
+    for (int c = 0; c < CPW; ++c)
+        asm volatile("" : "+v"(ev[c][0]), "+v"(ev[c][1]), "+v"(ev[c][2]), "+v"(ev[c][3]), "+v"(ev[c][4]),
+                     "+v"(ev[c][5]), "+v"(ev[c][6]), "+v"(ev[c][7]));
 #pragma unroll
     for (int c = 0; c < CPW; ++c) {
         acc[c] = 0.0f;
