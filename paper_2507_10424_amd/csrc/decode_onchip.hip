@@ -188,13 +188,16 @@ struct Job {
 // NMS: the learned check update (J.alpha, J.beta non-null); plain Min-Sum
 // instantiations carry no trace of it.
 // CF: the bank-conflict-free layout of the graph (layout.hip): rows and bits
-// in the thread slots its tables give, and every edge's message at a
-// position of its own that both passes read from LDS (so the previous
-// messages are not kept in registers); needs exact degrees and its
-// geometry (two rows, four bits per thread).
-template <int DC, bool RX, int DV, bool CX, int RPT, int CPT, int F, bool NMS, bool CF>
+// in the thread slots its tables give, and every edge's message at an LDS
+// position of its own; needs exact degrees and its geometry (two rows, four
+// bits per thread).  CF = 1: the check pass reads each edge's previous
+// message back from its position (no registers for them); CF = 2: it keeps
+// them in registers, as without the layout (a third fewer LDS reads).
+template <int DC, bool RX, int DV, bool CX, int RPT, int CPT, int F, bool NMS, int CF>
 __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t early, unsigned char *lds) {
-    static_assert(!CF || (RX && CX && RPT == 2 && CPT == 4 && F == 2), "layout geometry");
+    constexpr bool kLay = CF != 0;     // the layout's tables
+    constexpr bool kPrevLds = CF == 1; // previous messages read from LDS
+    static_assert(!kLay || (RX && CX && RPT == 2 && CPT == 4 && F == 2), "layout geometry");
     typedef typename Vec<F>::type V;
     constexpr uint32_t kEnt = sizeof(V); // bytes of one LDS entry (F floats)
     // read all s (messages) of the check (bit) pass up front when that takes
@@ -209,7 +212,7 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
     // the learned update only with exact row degrees, where its weights sit
     // in scalar registers and leave room for the 8, and not in the
     // conflict-free layout, whose bit-side message addresses take them
-    constexpr bool kAheadLLR = CPT * F <= 8 && CX && (!NMS || (RX && !CF));
+    constexpr bool kAheadLLR = CPT * F <= 8 && CX && (!NMS || (RX && !kLay));
     const int32_t *__restrict__ row_ptr = J.row_ptr;
     const uint32_t *__restrict__ edge_tab = J.edge_tab;
     const int32_t *__restrict__ col_ptr = J.col_ptr;
@@ -227,7 +230,7 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
     const int32_t ncls = J.ncls;
     uint32_t *__restrict__ queue = J.queue;
     const int32_t nq = J.nq;
-    const uint32_t eta0 = CF ? J.cf_eta_off : kEnt * (uint32_t)n; // byte offset of eta
+    const uint32_t eta0 = kLay ? J.cf_eta_off : kEnt * (uint32_t)n; // byte offset of eta
     Shared *sh = reinterpret_cast<Shared *>(lds + sh_off);
     const int tid = threadIdx.x;
     const int nt = blockDim.x;
@@ -238,7 +241,7 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
         const int32_t i = tid + r * nt;
-        if constexpr (CF) {
+        if constexpr (kLay) {
             // every slot has a table entry (slots past m: bit 0, the spare position)
             deg[r] = DC;
             rcls[r] = NMS ? J.cf_row_class[i] : 0;
@@ -272,12 +275,12 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
     // Own bit slots p = tid + c nt (LDS s at kEnt p): the bit index they hold
     // (frame I/O) and, in the layout, their messages' LDS addresses.
     int32_t gj[CPT];
-    uint32_t ba[CF ? CPT : 1][CF ? DV : 1];
+    uint32_t ba[kLay ? CPT : 1][kLay ? DV : 1];
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
         const int32_t p = tid + c * nt;
-        gj[c] = CF ? (p < n ? J.cf_slot_bit[p] : 0) : p;
-        if constexpr (CF) {
+        gj[c] = kLay ? (p < n ? J.cf_slot_bit[p] : 0) : p;
+        if constexpr (kLay) {
 #pragma unroll
             for (int u = 0; u < DV; ++u)
                 ba[c][u] = eta0 + kEnt * (p < n ? J.cf_bitpos[(size_t)p * DV + u] : (uint32_t)(J.cf_npos - 1));
@@ -347,7 +350,7 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
     for (int r = 0; r < RPT; ++r)
 #pragma unroll
         for (int k = 0; k < DC; ++k) eprev[r][k] = vzero<V>();
-    if constexpr (CF) { // every message starts at 0 (first iteration of every slot)
+    if constexpr (kPrevLds) { // every message starts at 0 (first iteration of every slot)
         for (int32_t e = tid; e < J.cf_npos; e += nt) lds_st<V>(lds, eta0 + kEnt * (uint32_t)e, vzero<V>());
     }
 #pragma unroll
@@ -385,14 +388,14 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
         // so the reads of later rows overlap the work of earlier ones.
         // In the layout (CF), each edge's previous message is read from its
         // LDS position as well, in the same batch.
-        V svp[RPT][DC], pvp[CF ? RPT : 1][CF ? DC : 1];
+        V svp[RPT][DC], pvp[kPrevLds ? RPT : 1][kPrevLds ? DC : 1];
         if constexpr (kPrefetchS) {
 #pragma unroll
             for (int r = 0; r < RPT; ++r)
 #pragma unroll
                 for (int k = 0; k < DC; ++k) {
                     svp[r][k] = lds_ld<V>(lds, sa[r][k]);
-                    if constexpr (CF) pvp[r][k] = lds_ld<V>(lds, ea[r][k]);
+                    if constexpr (kPrevLds) pvp[r][k] = lds_ld<V>(lds, ea[r][k]);
                 }
         }
         // per slot, the OR of the syndrome words of the own rows: its sign bit
@@ -408,7 +411,7 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
 #pragma unroll
             for (int k = 0; k < DC; ++k) {
                 sv[k] = kPrefetchS ? svp[r][k] : lds_ld<V>(lds, sa[r][k]);
-                if constexpr (CF) pv_[k] = kPrefetchS ? pvp[r][k] : lds_ld<V>(lds, ea[r][k]);
+                if constexpr (kPrevLds) pv_[k] = kPrefetchS ? pvp[r][k] : lds_ld<V>(lds, ea[r][k]);
                 else pv_[k] = eprev[r][k];
             }
 #pragma unroll
@@ -484,7 +487,7 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
             }
 #pragma unroll
             for (int k = 0; k < DC; ++k) {
-                if constexpr (!CF) eprev[r][k] = msg[k];
+                if constexpr (!kPrevLds) eprev[r][k] = msg[k];
                 if (RX || k < d) lds_st<V>(lds, ea[r][k], msg[k]); // rows past m write the padding slot
             }
         }
@@ -556,7 +559,7 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
             }
             fr[q] = nf;
             gen[q] += 1;
-            if constexpr (!CF) { // (CF: the bit pass zeroes the slot's messages in LDS)
+            if constexpr (!kPrevLds) { // (else the bit pass zeroes the slot's messages in LDS)
 #pragma unroll
                 for (int r = 0; r < RPT; ++r)
 #pragma unroll
@@ -590,7 +593,7 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
                 const int32_t dv = CX ? DV : (int32_t)(ckd[c] >> 16);
 #pragma unroll
                 for (int k = 0; k < DV; ++k)
-                    evp[c][k] = CF ? lds_ld<V>(lds, ba[CF ? c : 0][CF ? k : 0])
+                    evp[c][k] = kLay ? lds_ld<V>(lds, ba[kLay ? c : 0][kLay ? k : 0])
                                    : lds_ld<V>(lds, base + kEnt * (uint32_t)(CX || k < dv ? k : 0));
             }
         }
@@ -606,7 +609,7 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
 #pragma unroll
                 for (int k = 0; k < DV; ++k)
                     ev[k] = kPrefetchEta ? evp[c][k]
-                            : CF         ? lds_ld<V>(lds, ba[CF ? c : 0][CF ? k : 0])
+                            : kLay       ? lds_ld<V>(lds, ba[kLay ? c : 0][kLay ? k : 0])
                                          : lds_ld<V>(lds, base + kEnt * (uint32_t)(CX || k < dv ? k : 0));
                 V acc = (CX || 0 < dv) ? ev[0] : vzero<V>();
 #pragma unroll
@@ -631,10 +634,10 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
                                                       : (fr[q] < B ? llr[(size_t)fr[q] * n + gj[c]] + 0.0f : 0.0f);
                             rc[c][q] = v;
                             lds_st<float>(lds, kEnt * (uint32_t)j + 4u * (uint32_t)q, v);
-                            if constexpr (CF) { // the new frame's first iteration reads 0 messages
+                            if constexpr (kPrevLds) { // the new frame's first iteration reads 0 messages
 #pragma unroll
                                 for (int u = 0; u < DV; ++u)
-                                    lds_st<float>(lds, ba[CF ? c : 0][CF ? u : 0] + 4u * (uint32_t)q, 0.0f);
+                                    lds_st<float>(lds, ba[kLay ? c : 0][kLay ? u : 0] + 4u * (uint32_t)q, 0.0f);
                             }
                         }
                     }
@@ -654,8 +657,8 @@ struct Variant {
     bool cx;
     int rpt;
     int cpt;
-    int f;   // frame slots per workgroup
-    bool cf; // the graph's bank-conflict-free layout
+    int f;  // frame slots per workgroup
+    int cf; // the graph's bank-conflict-free layout: 0 no, 1 previous messages in LDS, 2 in registers
 };
 
 // Exact-degree variants for the regular codes in use first, then masked ones,
@@ -669,7 +672,8 @@ constexpr Variant kVariants[] = {
     {12, true, 8, false, 1, 4, 2}, {16, true, 8, false, 1, 8, 2}, {8, false, 8, false, 2, 4, 2},
     {16, false, 16, false, 1, 8, 2}, {6, true, 3, true, 1, 4, 2}, {6, true, 3, true, 2, 4, 4},
     {6, true, 3, true, 1, 4, 4},     {6, true, 6, false, 2, 4, 2},  {9, true, 6, false, 2, 8, 2},
-    {12, true, 6, false, 1, 4, 2},   {16, true, 6, false, 1, 8, 2}, {6, true, 3, true, 2, 4, 2, true},
+    {12, true, 6, false, 1, 4, 2},   {16, true, 6, false, 1, 8, 2}, {6, true, 3, true, 2, 4, 2, 1},
+    {6, true, 3, true, 2, 4, 2, 2},
 };
 constexpr int kNumVariants = (int)(sizeof(kVariants) / sizeof(kVariants[0]));
 
@@ -710,8 +714,8 @@ __global__ __launch_bounds__(kMaxThreads) __attribute__((amdgpu_waves_per_eu(W >
 // tables are built for the graph's own thread count, and the shared launch
 // runs the largest thread count of its jobs.
 constexpr int kWideVariant = 6;
-constexpr bool shared_launch_ok(int v) { return v != kWideVariant && !kVariants[v].cf; }
-static_assert(kNumVariants == 15, "k_onchip_multi dispatches variants 0-5 and 7-13");
+constexpr bool shared_launch_ok(int v) { return v != kWideVariant && kVariants[v].cf == 0; }
+static_assert(kNumVariants == 16, "k_onchip_multi dispatches variants 0-5 and 7-13");
 
 __global__ __launch_bounds__(kMaxThreads) void k_onchip_multi(const JobTable jt, int32_t L, int32_t early) {
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
@@ -741,7 +745,8 @@ using KernelFn = void (*)(const JobTable, int32_t, int32_t);
 #define LDPC_ONCHIP_ROW(W, N)                                                                                      \
     {&k_onchip<0, W, N>, &k_onchip<1, W, N>, &k_onchip<2, W, N>, &k_onchip<3, W, N>, &k_onchip<4, W, N>,         \
      &k_onchip<5, W, N>, &k_onchip<6, W, N>, &k_onchip<7, W, N>, &k_onchip<8, W, N>, &k_onchip<9, W, N>,         \
-     &k_onchip<10, W, N>, &k_onchip<11, W, N>, &k_onchip<12, W, N>, &k_onchip<13, W, N>, &k_onchip<14, W, N>}
+     &k_onchip<10, W, N>, &k_onchip<11, W, N>, &k_onchip<12, W, N>, &k_onchip<13, W, N>, &k_onchip<14, W, N>,        \
+     &k_onchip<15, W, N>}
 const KernelFn kKernels[2][2][kNumVariants] = {{LDPC_ONCHIP_ROW(0, false), LDPC_ONCHIP_ROW(4, false)},
                                                {LDPC_ONCHIP_ROW(0, true), LDPC_ONCHIP_ROW(4, true)}};
 #undef LDPC_ONCHIP_ROW
@@ -760,22 +765,22 @@ bool variant_ok(const ldpc_graph &g, int k) {
     const bool rows_ok = v.rx ? (g.dc_min == v.dc && g.dc_max == v.dc) : g.dc_max <= v.dc;
     const bool cols_ok = v.cx ? (g.dv_min == v.dv && g.dv_max == v.dv) : g.dv_max <= v.dv;
     // the layout's tables are for exact degrees and their own thread count
-    const bool cf_ok = !v.cf || (g.cf.edge != nullptr && g.dc_min == v.dc && g.dv_min == v.dv &&
+    const bool cf_ok = v.cf == 0 || (g.cf.edge != nullptr && g.dc_min == v.dc && g.dv_min == v.dv &&
                                  threads_for(g, v) == g.cf.nt);
-    const size_t state = v.cf ? cf_state_bytes(g) : state_bytes(g, v.f);
+    const size_t state = v.cf != 0 ? cf_state_bytes(g) : state_bytes(g, v.f);
     return rows_ok && cols_ok && cf_ok && threads_for(g, v) <= kMaxThreads && g.edge_tab != nullptr &&
            state + sizeof(Shared) + 1024 <= (size_t)g.lds_max;
 }
 
 size_t state_of(const ldpc_graph &g, int variant) {
-    return kVariants[variant].cf ? cf_state_bytes(g) : state_bytes(g, kVariants[variant].f);
+    return kVariants[variant].cf != 0 ? cf_state_bytes(g) : state_bytes(g, kVariants[variant].f);
 }
 size_t lds_of(const ldpc_graph &g, int variant) { return state_of(g, variant) + sizeof(Shared); }
 
 // Default preference when nothing is tuned: the bank-conflict-free layout,
 // then exact degrees, a column mask of 6 before one of 8, two frame slots
 // before four.
-constexpr int kPickOrder[] = {14, 0, 7, 10, 1, 11, 2, 12, 3, 13, 4, 5, 6, 8, 9};
+constexpr int kPickOrder[] = {15, 14, 0, 7, 10, 1, 11, 2, 12, 3, 13, 4, 5, 6, 8, 9};
 static_assert(sizeof(kPickOrder) / sizeof(kPickOrder[0]) == kNumVariants, "every variant has a place");
 
 // The tuned variant if one is set and valid, else the first that fits.

@@ -165,3 +165,29 @@ def test_big_jobs_of_one_kernel_share_a_launch(tdev):
         assert launches.value == 3
         for k, o in enumerate(outs):
             assert_parity(tuple(t.cpu().numpy() for t in o), refs[k], f"shared launch job {k} rep {rep}")
+
+
+def test_qc_family_configured_batches_one_call(tdev):
+    """The eight QC codes at their configured batches (512 to 16,384 frames,
+    41,472 in all) in one ldpc_minsum_decode_multi call, as the benchmark runs
+    them: every output of a sample of each code's frames (its first and last
+    frames and a seeded random draw) equals the oracle's."""
+    torch, dev = tdev
+    from paper_2507_10424_amd import ldpc
+    fam = wl.qc_multi_code_family(seed=7)
+    jobs, inputs = [], []
+    for k, c in enumerate(fam):
+        llr = wl.bpsk_awgn_llr(None, 2.0, c["rate"], seed=300 + k, n=c["n"], batch=c["batch"])
+        g = ldpc.build_graph(torch.from_numpy(c["H"]).to(dev))
+        jobs.append((g, torch.from_numpy(llr).to(dev)))
+        inputs.append((c["H"], llr))
+    note(f"[multi] configured batches {[c['batch'] for c in fam]}")
+    outs = ldpc.minsum_decode_multi(jobs, 50)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(11)
+    for k, ((H, llr), o) in enumerate(zip(inputs, outs)):
+        B = llr.shape[0]
+        pick = np.unique(np.concatenate([np.arange(24), np.arange(B - 24, B), rng.choice(B, 48, replace=False)]))
+        got = tuple(t.cpu().numpy()[pick] for t in o)
+        note(f"[multi] code {k}: n={H.shape[1]} B={B}, {pick.size} frames checked, mean iters {got[2].mean():.2f}")
+        assert_parity(got, oracle_decode(H, llr[pick], 50), f"configured batch, code {k}")

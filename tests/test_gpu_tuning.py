@@ -28,7 +28,7 @@ def test_all_launch_choices_agree(tdev):
     llr = torch.from_numpy(llr_np).to(dev)
     ref = oracle_decode(H, llr_np, 40)
     tried = 0
-    for v, wpc, wps in itertools.product(range(14), (0, 1, 3), (0, 4)):
+    for v, wpc, wps in itertools.product(range(16), (0, 1, 3), (0, 4)):
         try:
             ldpc.set_tuning(g, 1, variant=v, wg_per_cu=wpc, waves_per_simd=wps)
         except ldpc.LdpcError as e:
@@ -43,7 +43,18 @@ def test_all_launch_choices_agree(tdev):
         out = ldpc.minsum_decode(g, llr, 40)
         torch.cuda.synchronize()
         assert_parity(tuple(t.cpu().numpy() for t in out), ref, f"stream waves {waves} non-temporal {nt}")
-    assert tried >= 4 * 3 * 2
+    assert tried >= 6 * 3 * 2
+    # the learned update in both forms of the bank-conflict-free layout
+    rng = np.random.default_rng(5)
+    T = 40
+    alpha = rng.uniform(0.6, 1.1, size=(T, 1)).astype(np.float32)
+    beta = rng.uniform(0.0, 0.3, size=(T, 1)).astype(np.float32)
+    ref_nms = oracle_decode(H, llr_np, T, alpha=alpha, beta=beta)
+    for v in (14, 15):
+        ldpc.set_tuning(g, 1, variant=v, waves_per_simd=4)
+        out = ldpc.nms_decode(g, llr, T, torch.from_numpy(alpha).to(dev), torch.from_numpy(beta).to(dev))
+        torch.cuda.synchronize()
+        assert_parity(tuple(t.cpu().numpy() for t in out), ref_nms, f"learned, variant {v}")
     ldpc.set_tuning(g, None)
     assert ldpc.get_tuning(g)["path"] == 0
 
