@@ -37,11 +37,11 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # 32-bit VALU lane-ops/s: 256 CUs x 64
 # the run uses other choices, the figure no longer applies and `traffic` is
 # reported as null.  Summaries: profiles/hbm_bytes_qc64800_regular1024.md.
 MEASURED_TRAFFIC = {
-    ("regular1024", "onchip"): {"bytes": 609696486, "source": "decode_onchip.hip", "sha256_16": "4f5e8e0929207271"},
-    ("qc64800", "check"): {"bytes": 322232778, "source": "decode_stream.hip", "sha256_16": "c2a60f69bb9effb6",
-                           "tuning": {"path": 2, "stream_nt": 0, "stream_chunk": -1}},
-    ("qc64800", "bit"): {"bytes": 178164538, "source": "decode_stream.hip", "sha256_16": "c2a60f69bb9effb6",
-                         "tuning": {"path": 2, "stream_nt": 0, "stream_chunk": -1}},
+    ("regular1024", "onchip"): {"bytes": 609768206, "source": "decode_onchip.hip", "sha256_16": "00d9b366466b6e53"},
+    ("qc64800", "check"): {"bytes": 322257345, "source": "decode_stream.hip", "sha256_16": "da28e014ff411285",
+                           "tuning": {"path": 2, "stream_nt": -1, "stream_chunk": -1}},
+    ("qc64800", "bit"): {"bytes": 178182331, "source": "decode_stream.hip", "sha256_16": "da28e014ff411285",
+                         "tuning": {"path": 2, "stream_nt": -1, "stream_chunk": -1}},
 }
 
 
