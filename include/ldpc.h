@@ -327,8 +327,9 @@ int ldpc_adam_step(float *param_dev, const float *grad_dev, float *m1_dev, float
  *                 per thread, frame slots), -1 for the preferred one
  *   wg_per_cu     on-chip workgroups per CU, 0 for the occupancy limit
  *   stream_waves  wavefronts per workgroup of the streaming kernels (1..8)
- *   waves_per_simd  on-chip register budget: 0 the compiler's, 4 at least four
- *                 resident waves per SIMD (fewer registers per thread)
+ *   waves_per_simd  on-chip register budget: 0 the compiler's, 4 (3) at least
+ *                 four (three) resident waves per SIMD (fewer registers per
+ *                 thread)
  *   ms            ldpc_autotune: mean time of one decode of the tuning batch
  *   stream_nt     streaming path: 1 marks the message loads and stores
  *                 non-temporal (they stream through the caches and leave them

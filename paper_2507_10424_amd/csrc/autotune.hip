@@ -3,7 +3,7 @@
 //
 // Choices: the on-chip path with each kernel variant that fits the graph
 // (exact or masked degree templates, one or two rows per thread), a register
-// budget (the compiler's, or at least 4 waves per SIMD) and a cap on
+// budget (the compiler's, or at least 4 or 3 waves per SIMD) and a cap on
 // workgroups per CU (occupancy limit, 1, 2, 3, 4); the streaming path with
 // 1, 2, 4 or 8 wavefronts per workgroup of its check and bit kernels.
 #include <vector>
@@ -73,7 +73,8 @@ extern "C" int ldpc_graph_set_tuning(ldpc_graph *g, const ldpc_tuning *t) {
     if (t->path == 2 && (t->stream_waves < 1 || t->stream_waves > 8)) return LDPC_EINVAL;
     if (t->stream_nt < -1 || t->stream_nt > 1) return LDPC_EINVAL;
     if (t->stream_chunk < -1) return LDPC_EINVAL;
-    if (t->path == 1 && t->waves_per_simd != 0 && t->waves_per_simd != 4) return LDPC_EINVAL;
+    if (t->path == 1 && t->waves_per_simd != 0 && t->waves_per_simd != 3 && t->waves_per_simd != 4)
+        return LDPC_EINVAL;
     g->tuning.set = true;
     g->tuning.path = t->path;
     g->tuning.variant = t->variant;
@@ -120,15 +121,22 @@ extern "C" int ldpc_autotune(ldpc_graph *g, int32_t B, int32_t max_iter, float e
     if (st) return st;
 
     std::vector<ldpc_tuning> cands;
-    // Kernels that spill are never the fastest where a spill-free one fits;
-    // they stay candidates only for graphs that nothing else fits.
+    // A kernel that spills under the compiler's own budget stays a candidate
+    // only for graphs that no spill-free one fits.  Under a tighter budget
+    // spills are timed like anything else: the compiler tends to put them in
+    // the set-up and refill code, outside the rounds.  A tighter budget is
+    // only tried where it differs from the compiler's (which takes more than
+    // a quarter, or a third, of the 512 registers).
     bool clean_fit = false;
     for (int v = 0; v < onchip_num_variants(); ++v)
         clean_fit = clean_fit || (onchip_variant_fits(*g, v) && onchip_kernel_spill_free(v, 0));
     for (int v = 0; v < onchip_num_variants(); ++v) {
         if (!onchip_variant_fits(*g, v)) continue;
-        for (int wps : {0, 4}) {
-            if (!onchip_kernel_spill_free(v, wps) && (wps == 4 || clean_fit)) continue;
+        const int regs = onchip_kernel_vgprs(v, 0);
+        for (int wps : {0, 4, 3}) {
+            if (wps == 0 && !onchip_kernel_spill_free(v, 0) && clean_fit) continue;
+            if (wps == 4 && regs >= 0 && regs <= 128) continue;
+            if (wps == 3 && regs >= 0 && regs <= 168) continue;
             for (int wpc : {0, 1, 2, 3, 4}) cands.push_back(ldpc_tuning{1, v, wpc, 4, wps, 0.0f, -1, -1});
         }
     }

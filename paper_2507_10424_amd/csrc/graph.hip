@@ -170,6 +170,7 @@ void free_graph_arrays(ldpc_graph *g) {
     g->cf.edge = g->cf.bitpos = nullptr;
     g->cf.slot_bit = g->cf.row_class = nullptr;
     g->cf.nt = g->cf.npos = 0;
+    g->cf.rpt = g->cf.cpt = g->cf.dvs = 0;
     g->row_ptr = g->col_idx = g->col_ptr = g->csc_edge = g->row_class = g->edge_pos = nullptr;
     g->edge_tab = nullptr;
     g->dense_h = nullptr;
@@ -298,11 +299,13 @@ int build(const uint8_t *H, int32_t m, int32_t n, hipStream_t s, ldpc_graph *g) 
                 fail(LDPC_EHIP);
                 break;
             }
-            // the bank-conflict-free layout, for one row and one column degree
+            // the bank-conflict-free layout, for rows of one degree, in the
+            // geometry of the layout variants that fits the graph best
             ldpc::OnchipLayout lay;
-            if (E > 0 && g->dc_min == g->dc_max && g->dv_min == g->dv_max &&
-                ldpc::onchip_cf_layout(h_rowptr, h_bit, h_class, m, n, &lay)) {
-                const size_t S = (size_t)ldpc::OnchipLayout::kRpt * lay.nt;
+            int32_t rpt = 0, cpt = 0, dvs = 0;
+            if (E > 0 && g->dc_min == g->dc_max && ldpc::onchip_cf_geometry(*g, &rpt, &cpt, &dvs) &&
+                ldpc::onchip_cf_layout(h_rowptr, h_bit, h_class, m, n, rpt, cpt, dvs, &lay)) {
+                const size_t S = (size_t)lay.rpt * lay.nt;
                 if (dalloc(&g->cf.edge, lay.edge.size()) != hipSuccess ||
                     dalloc(&g->cf.bitpos, lay.bitpos.size()) != hipSuccess ||
                     dalloc(&g->cf.slot_bit, lay.slot_bit.size()) != hipSuccess ||
@@ -323,6 +326,9 @@ int build(const uint8_t *H, int32_t m, int32_t n, hipStream_t s, ldpc_graph *g) 
                 }
                 g->cf.nt = lay.nt;
                 g->cf.npos = lay.npos;
+                g->cf.rpt = lay.rpt;
+                g->cf.cpt = lay.cpt;
+                g->cf.dvs = lay.dv;
             }
         }
     } while (false);

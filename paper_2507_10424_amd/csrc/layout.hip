@@ -8,8 +8,8 @@
 // modulo 16.  Measured: ds_read_b64 2.5 cycles per wavefront instruction and CU
 // conflict-free, 7.5 with random addresses; ds_write_b64 6.2 and 11.9.
 //
-// The on-chip decoder's LDS traffic per round (two rows and four bits per
-// thread) is: in the check pass, per own row and edge, a read of the bit's
+// The on-chip decoder's LDS traffic per round (a geometry of rpt rows and cpt
+// bits per thread) is: in the check pass, per own row and edge, a read of the bit's
 // posterior s (a gather), a read of the edge's previous message and a write
 // of its new one; in the bit pass, per own bit, reads of its column's
 // messages (a gather) and a write of s.  The layout chooses
@@ -18,8 +18,10 @@
 //     depend on it),
 //   * and a free LDS position for every edge's message,
 // so that every message read and write is conflict-free and the posterior
-// gathers nearly so.  Bits keep their own index as their slot (so frame I/O
-// stays coalesced).
+// gathers nearly so.  Bits move only inside their 64-slot block (so frame I/O
+// stays coalesced).  Columns of lower degree than the table's stride, and bit
+// slots past n, read zero messages from positions that nothing writes: their
+// bit sums then take the same instructions as the others and stay exact.
 //
 // Message positions are exact by construction.  Give each edge a class c in
 // 0..31 (its position is c modulo 32).  Its write (check pass) falls in one
@@ -99,20 +101,20 @@ std::vector<int32_t> bipartite_edge_colour(int32_t nleft, int32_t nright, const 
 } // namespace
 
 bool onchip_cf_layout(const std::vector<int32_t> &rowptr, const std::vector<int32_t> &col,
-                      const std::vector<int32_t> &row_class, int32_t m, int32_t n, OnchipLayout *out) {
-    constexpr int32_t kRpt = OnchipLayout::kRpt, kCpt = OnchipLayout::kCpt;
-    const int64_t E = (int64_t)col.size();
-    if (m < 1 || n < 1 || E < 1 || n >= 65536 || E >= 65536) return false;
+                      const std::vector<int32_t> &row_class, int32_t m, int32_t n, int32_t rpt, int32_t cpt,
+                      int32_t dvs, OnchipLayout *out) {
+        const int64_t E = (int64_t)col.size();
+    if (m < 1 || n < 1 || E < 1 || n >= 65536 || E >= 65536 || rpt < 1 || cpt < 1) return false;
     int32_t dc = 0;
     for (int32_t i = 0; i < m; ++i) dc = std::max(dc, rowptr[i + 1] - rowptr[i]);
     std::vector<int32_t> cdeg(n, 0);
     for (int32_t j : col) ++cdeg[j];
     const int32_t dv = *std::max_element(cdeg.begin(), cdeg.end());
-    if (dc > 16 || dv > 16) return false;
-    const int32_t need = std::max((m + kRpt - 1) / kRpt, (n + kCpt - 1) / kCpt);
+    if (dc > 16 || dv > 16 || dvs < dv || dvs > 16) return false;
+    const int32_t need = std::max((m + rpt - 1) / rpt, (n + cpt - 1) / cpt);
     const int32_t nt = std::max<int32_t>(64, (need + 63) / 64 * 64);
     if (nt > 512) return false;
-    const int32_t S = kRpt * nt;      // row slots: s = r nt + t
+    const int32_t S = rpt * nt;        // row slots: s = r nt + t
     const int32_t G = S / 32;         // half-groups of 32 row slots
     auto group_of = [&](int32_t s) { return (s / nt) * (nt / 32) + (s % nt) / 32; };
 
@@ -250,7 +252,7 @@ bool onchip_cf_layout(const std::vector<int32_t> &rowptr, const std::vector<int3
     const int32_t nw = nt / 64;
     auto chk_quarter = [&](int64_t e, int32_t i) {
         const int32_t s = row_slot[i], r = s / nt, t = s % nt;
-        return (((int64_t)(t / 64) * kRpt + r) * 16 + kpos[e]) * 4 + (t % 64) / 16;
+        return (((int64_t)(t / 64) * rpt + r) * 16 + kpos[e]) * 4 + (t % 64) / 16;
     };
     auto bit_half = [&](int64_t e) {
         const int32_t j = bit_slot[col[e]], c = j / nt, t = j % nt;
@@ -339,14 +341,20 @@ bool onchip_cf_layout(const std::vector<int32_t> &rowptr, const std::vector<int3
         pos[e] = c + 32 * used[c]++;
     }
     const int32_t rows32 = *std::max_element(used.begin(), used.end());
-    const int32_t dummy = 32 * rows32;   // one more position: rows past m read and write it
+    // 32 zero positions (one per class, never written but with zeros) for the
+    // bit-side entries past a bit's degree and for bit slots past n, then one
+    // position that rows past m read and write
+    const int32_t zero = 32 * rows32;
+    const int32_t dummy = zero + 32;
     const int32_t npos = dummy + 1;
     if (npos >= 65536) return false;
 
     // ---- tables
     out->nt = nt;
+    out->rpt = rpt;
+    out->cpt = cpt;
     out->dc = dc;
-    out->dv = dv;
+    out->dv = dvs;
     out->npos = npos;
     out->edge.assign((size_t)S * dc, (uint32_t)dummy << 16); // bit 0's s, the dummy position
     out->row_class.assign(S, 0);
@@ -356,10 +364,28 @@ bool onchip_cf_layout(const std::vector<int32_t> &rowptr, const std::vector<int3
         for (int32_t e = rowptr[i]; e < rowptr[i + 1]; ++e)
             out->edge[(size_t)s * dc + kpos[e]] = (uint32_t)bit_slot[col[e]] | ((uint32_t)pos[e] << 16);
     }
-    out->bitpos.assign((size_t)n * dv, (uint32_t)dummy);
+    const int32_t P = cpt * nt; // bit slots
+    out->bitpos.assign((size_t)P * dvs, 0xffffffffu);
     for (int32_t i = 0; i < m; ++i)
         for (int32_t e = rowptr[i]; e < rowptr[i + 1]; ++e)
-            out->bitpos[(size_t)bit_slot[col[e]] * dv + rank[e]] = (uint32_t)pos[e];
+            out->bitpos[(size_t)bit_slot[col[e]] * dvs + rank[e]] = (uint32_t)pos[e];
+    // Entries without a message read a zero position in a class that no real
+    // entry of their bit instruction's half uses (the real ones are distinct
+    // modulo 32, so at most 31 classes are taken when one entry is missing).
+    for (int32_t base = 0; base < P; base += 32)
+        for (int32_t u = 0; u < dvs; ++u) {
+            uint32_t taken = 0u;
+            for (int32_t p = base; p < base + 32; ++p) {
+                const uint32_t v = out->bitpos[(size_t)p * dvs + u];
+                if (v != 0xffffffffu) taken |= 1u << (v % 32);
+            }
+            int32_t c = 0;
+            while (c < 32 && ((taken >> c) & 1u)) ++c;
+            for (int32_t p = base; p < base + 32; ++p) {
+                uint32_t &v = out->bitpos[(size_t)p * dvs + u];
+                if (v == 0xffffffffu) v = (uint32_t)(zero + (c < 32 ? c : 0));
+            }
+        }
     out->slot_bit.assign(slot_bit.begin(), slot_bit.begin() + n);
     return true;
 }

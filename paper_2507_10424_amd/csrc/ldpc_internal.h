@@ -33,13 +33,14 @@ struct ldpc_graph {
     // the bit index in the low 16 bits and the CSC slot in the high 16 bits.
     uint32_t *edge_tab = nullptr; // E, or null
     // Bank-conflict-free on-chip layout (OnchipLayout), built for graphs with
-    // one row degree and one column degree that fit it; null otherwise.
+    // one row degree that a layout variant fits; null otherwise.
     struct {
         uint32_t *edge = nullptr;     // [row slot][k]: bit slot | message position << 16
         uint32_t *bitpos = nullptr;   // [bit slot][u]: message position
         int32_t *slot_bit = nullptr;  // [bit slot]: bit index
         int32_t *row_class = nullptr; // [row slot]: degree class
         int32_t nt = 0, npos = 0;     // threads of its geometry, message positions
+        int32_t rpt = 0, cpt = 0, dvs = 0; // rows and bits per thread, bit-side stride
     } cf;
     // Device copy of the dense m x n H (0/1 bytes) for the dense map-reduce
     // decoder, kept when m * n <= kDenseMaxBytes; null otherwise.
@@ -50,7 +51,7 @@ struct ldpc_graph {
         int path = 0;         // 1 on-chip, 2 streaming
         int variant = -1;     // on-chip kernel variant
         int wg_per_cu = 0;    // on-chip workgroups per CU (0: occupancy limit)
-        int waves_per_simd = 0; // on-chip register budget: 0 compiler's, 4 at least 4 waves per SIMD
+        int waves_per_simd = 0; // on-chip register budget: 0 compiler's, 4 / 3 at least 4 / 3 waves per SIMD
         int stream_waves = 4; // wavefronts per workgroup of the streaming kernels
         int stream_nt = -1;   // non-temporal message accesses: 1 yes, 0 no, -1 by size
         int stream_chunk = -1; // tiles per chunk of the streaming path: 0 all, -1 by size
@@ -81,27 +82,34 @@ bool onchip_variant_fits(const ldpc_graph &g, int variant);
 int onchip_num_variants();
 // Whether the kernel of (variant, register budget) needs no scratch (no spills).
 bool onchip_kernel_spill_free(int variant, int waves_per_simd);
+// Vector registers per thread of that kernel (-1 if unknown).
+int onchip_kernel_vgprs(int variant, int waves_per_simd);
 size_t onchip_workspace_bytes(const ldpc_graph &g, int32_t B);
 int onchip_decode(const ldpc_graph &g, const float *llr, int32_t B, int32_t L, uint32_t flags,
                   const float *alpha, const float *beta, int32_t T, uint8_t *bits, float *post,
                   int32_t *iters, uint8_t *ok, void *ws, size_t ws_bytes, hipStream_t stream);
 
-// Bank-conflict-free on-chip layout (layout.hip) for a geometry of kRpt
-// rows and kCpt bits per thread: check row slot s = r nt + t and bit slot
-// p = c nt + t hold the row and bit given by the tables (a bit stays in its
-// 64-slot block, slots n and up are empty).
+// Bank-conflict-free on-chip layout (layout.hip) for a geometry of rpt rows
+// and cpt bits per thread: check row slot s = r nt + t and bit slot p = c nt + t
+// hold the row and bit given by the tables (a bit stays in its 64-slot block,
+// slots n and up are empty).  The bit-side table has a stride of dv >= the
+// largest column degree; entries past a bit's degree name zero positions.
 struct OnchipLayout {
-    static constexpr int kRpt = 2, kCpt = 4;
-    int32_t nt = 0;    // threads
-    int32_t dc = 0, dv = 0; // largest row / column degree
-    int32_t npos = 0;  // message positions (the last one for rows past m)
+    int32_t nt = 0;         // threads
+    int32_t rpt = 0, cpt = 0; // rows / bits per thread
+    int32_t dc = 0, dv = 0; // largest row degree, bit-side stride
+    int32_t npos = 0;       // message positions (the last one for rows past m)
     std::vector<uint32_t> edge;      // [row slot][k]: bit slot | message position << 16
-    std::vector<uint32_t> bitpos;    // [bit slot][u]: message position of the bit's u-th check (ascending)
+    std::vector<uint32_t> bitpos;    // [bit slot < cpt nt][u]: message position of the bit's u-th check (ascending)
     std::vector<int32_t> slot_bit;   // [bit slot < n]: the bit it holds
     std::vector<int32_t> row_class;  // [slot]: degree class of the row (0 past m)
 };
 bool onchip_cf_layout(const std::vector<int32_t> &rowptr, const std::vector<int32_t> &col,
-                      const std::vector<int32_t> &row_class, int32_t m, int32_t n, OnchipLayout *out);
+                      const std::vector<int32_t> &row_class, int32_t m, int32_t n, int32_t rpt, int32_t cpt,
+                      int32_t dvs, OnchipLayout *out);
+// The layout geometry the on-chip variants offer for a graph (rows of one
+// degree): rows and bits per thread and bit-side stride; false if none fits.
+bool onchip_cf_geometry(const ldpc_graph &g, int32_t *rpt, int32_t *cpt, int32_t *dvs);
 
 // Several graphs in one on-chip launch.
 size_t onchip_multi_workspace_bytes(int32_t njobs);

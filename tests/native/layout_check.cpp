@@ -1,13 +1,17 @@
 // Checks the on-chip decoder's bank-conflict-free layout (csrc/layout.hip)
-// on one graph read from stdin ("m n" then, per row, its degree and bits):
-// every row slot below m holds a distinct row with its own edges, each bit
-// sits in a slot of its own 64-slot block, every message has a position of
-// its own, the bit-side table lists each bit's messages in ascending check
-// order, and no two lanes of a message access conflict on the LDS banks
-// (writes: distinct positions modulo 16 per 16 lanes; reads: modulo 32 per
-// 32 lanes).  Prints "ok <mean max posterior-gather load>" or a failure.
+// on one graph read from stdin ("m n" then, per row, its degree and bits),
+// in the geometry given on the command line (rows and bits per thread,
+// bit-side stride; default 2 4 and the largest column degree): every row
+// slot below m holds a distinct row with its own edges, each bit sits in a
+// slot of its own 64-slot block, every message has a position of its own,
+// the bit-side table lists each bit's messages in ascending check order and
+// zero positions past its degree, and no two lanes of a message access
+// conflict on the LDS banks (writes: distinct positions modulo 16 per 16
+// lanes; reads: distinct words modulo 32 per 32 lanes).  Prints "ok <mean
+// max posterior-gather load>" or a failure.
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <vector>
 
 #include "ldpc_internal.h"
@@ -17,7 +21,7 @@ static int fail(const char *what) {
     return 1;
 }
 
-int main() {
+int main(int argc, char **argv) {
     int m, n;
     if (std::scanf("%d %d", &m, &n) != 2) return fail("input");
     std::vector<int32_t> rowptr(m + 1, 0), col, rc(m, 0);
@@ -31,10 +35,16 @@ int main() {
         }
         rowptr[i + 1] = (int32_t)col.size();
     }
+    std::vector<int> cdeg(n, 0);
+    for (int j : col) ++cdeg[j];
+    const int dmax = *std::max_element(cdeg.begin(), cdeg.end());
+    const int rpt = argc > 1 ? std::atoi(argv[1]) : 2, cpt = argc > 2 ? std::atoi(argv[2]) : 4;
+    const int dvs = argc > 3 ? std::atoi(argv[3]) : dmax;
     ldpc::OnchipLayout L;
-    if (!ldpc::onchip_cf_layout(rowptr, col, rc, m, n, &L)) return fail("no layout");
-    const int nt = L.nt, dc = L.dc, dv = L.dv, S = ldpc::OnchipLayout::kRpt * nt;
-    if ((int)L.edge.size() != S * dc || (int)L.bitpos.size() != n * dv || (int)L.slot_bit.size() != n)
+    if (!ldpc::onchip_cf_layout(rowptr, col, rc, m, n, rpt, cpt, dvs, &L)) return fail("no layout");
+    const int nt = L.nt, dc = L.dc, dv = L.dv, S = rpt * nt, P = cpt * nt;
+    if (L.rpt != rpt || L.cpt != cpt || dv != dvs || S < m || P < n) return fail("geometry");
+    if ((int)L.edge.size() != S * dc || (int)L.bitpos.size() != P * dv || (int)L.slot_bit.size() != n)
         return fail("table sizes");
     // bits: a permutation of 0..n-1 inside 64-slot blocks
     std::vector<int> bit_slot(n, -1);
@@ -79,11 +89,24 @@ int main() {
             rows_of_bit[gb[k]].push_back(row);
         }
     }
-    // bit side: the u-th entry is the message of the u-th check in ascending order
+    // bit side: the u-th entry is the message of the u-th check in ascending
+    // order, then zero positions (never a message's, never the rows-past-m one)
+    int nmsg = 0;
+    for (int p = 0; p < L.npos; ++p) nmsg += used[p];
+    if (nmsg != (int)col.size()) return fail("message count");
+    auto is_zero = [&](uint32_t p) { return (int)p < L.npos - 1 && !used[p]; };
+    for (int p = n; p < P; ++p)
+        for (int u = 0; u < dv; ++u)
+            if (!is_zero(L.bitpos[(size_t)p * dv + u])) return fail("empty bit slot reads a message");
     for (int j = 0; j < n; ++j) {
         std::vector<int> r = rows_of_bit[j];
         std::sort(r.begin(), r.end());
+        if ((int)r.size() != cdeg[j]) return fail("column degree");
         for (int u = 0; u < dv; ++u) {
+            if (u >= (int)r.size()) {
+                if (!is_zero(L.bitpos[(size_t)bit_slot[j] * dv + u])) return fail("padding entry");
+                continue;
+            }
             const int i = r[u];
             const int e = rowptr[i] + (int)(std::lower_bound(col.begin() + rowptr[i], col.begin() + rowptr[i + 1], j) -
                                             (col.begin() + rowptr[i]));
@@ -94,7 +117,7 @@ int main() {
     double load = 0;
     int halves = 0;
     for (int w = 0; w < nt / 64; ++w)
-        for (int r = 0; r < ldpc::OnchipLayout::kRpt; ++r)
+        for (int r = 0; r < rpt; ++r)
             for (int k = 0; k < dc; ++k) {
                 for (int q = 0; q < 4; ++q) {
                     int cnt[16] = {0};
@@ -120,15 +143,17 @@ int main() {
                     ++halves;
                 }
             }
-    for (int c = 0; c < ldpc::OnchipLayout::kCpt; ++c)
+    for (int c = 0; c < cpt; ++c)
         for (int w = 0; w < nt / 64; ++w)
             for (int u = 0; u < dv; ++u)
                 for (int h = 0; h < 2; ++h) {
                     int cnt[32] = {0};
+                    std::vector<uint32_t> words;
                     for (int l = 32 * h; l < 32 * h + 32; ++l) {
-                        const int p = c * nt + 64 * w + l;
-                        if (p < n && ++cnt[L.bitpos[(size_t)p * dv + u] % 32] > 1)
-                            return fail("message read conflict (bit pass)");
+                        const uint32_t v = L.bitpos[(size_t)(c * nt + 64 * w + l) * dv + u];
+                        if (std::find(words.begin(), words.end(), v) != words.end()) continue; // same word
+                        words.push_back(v);
+                        if (++cnt[v % 32] > 1) return fail("message read conflict (bit pass)");
                     }
                 }
     std::printf("ok %.4f\n", load / halves);

@@ -28,7 +28,7 @@ def test_all_launch_choices_agree(tdev):
     llr = torch.from_numpy(llr_np).to(dev)
     ref = oracle_decode(H, llr_np, 40)
     tried = 0
-    for v, wpc, wps in itertools.product(range(16), (0, 1, 3), (0, 4)):
+    for v, wpc, wps in itertools.product(range(32), (0, 1, 3), (0, 4)):
         try:
             ldpc.set_tuning(g, 1, variant=v, wg_per_cu=wpc, waves_per_simd=wps)
         except ldpc.LdpcError as e:
@@ -173,3 +173,42 @@ def test_kernel_timing_changes_no_output(tdev):
         for a, b in zip(ref, got):
             if a is not None:
                 assert torch.equal(a, b), name
+
+
+def test_every_variant_on_qc_family(tdev):
+    """Every on-chip variant that fits each of the eight QC codes (row degrees
+    6, 9, 12, 16; bit degrees 2/3/6 or 2/3/4), at both register budgets,
+    decodes like the oracle, plain and learned: among them the one-slot
+    variants, the bit degree masked at 4 and the bank-conflict-free layout
+    with columns padded to its stride."""
+    torch, dev = tdev
+    from paper_2507_10424_amd import ldpc
+    fam = wl.qc_multi_code_family(seed=7)
+    for k, c in enumerate(fam):
+        B = 90 + 13 * k
+        llr_np = wl.bpsk_awgn_llr(None, 2.0, c["rate"], seed=400 + k, n=c["n"], batch=B)
+        ref = oracle_decode(c["H"], llr_np, 30)
+        g = ldpc.build_graph(torch.from_numpy(c["H"]).to(dev))
+        llr = torch.from_numpy(llr_np).to(dev)
+        # the learned update on the first 40 frames
+        T = 30
+        rng = np.random.default_rng(60 + k)
+        alpha = rng.uniform(0.6, 1.1, size=(T, 1)).astype(np.float32)
+        beta = rng.uniform(0.0, 0.3, size=(T, 1)).astype(np.float32)
+        ref_nms = oracle_decode(c["H"], llr_np[:40], T, alpha=alpha, beta=beta)
+        al, be = torch.from_numpy(alpha).to(dev), torch.from_numpy(beta).to(dev)
+        tried = 0
+        for v, wps in itertools.product(range(32), (0, 4, 3)):
+            try:
+                ldpc.set_tuning(g, 1, variant=v, waves_per_simd=wps)
+            except ldpc.LdpcError as e:
+                assert e.status == -6
+                continue
+            out = ldpc.minsum_decode(g, llr, 30)
+            torch.cuda.synchronize()
+            assert_parity(tuple(t.cpu().numpy() for t in out), ref, f"code {k} variant {v} wps {wps}")
+            out = ldpc.nms_decode(g, llr[:40].contiguous(), T, al, be)
+            torch.cuda.synchronize()
+            assert_parity(tuple(t.cpu().numpy() for t in out), ref_nms, f"learned, code {k} variant {v} wps {wps}")
+            tried += 1
+        assert tried >= 2, f"code {k}: no variant fits"

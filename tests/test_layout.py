@@ -28,13 +28,13 @@ def checker(tmp_path_factory):
     return out
 
 
-def run(checker, H):
+def run(checker, H, geometry=()):
     m, n = H.shape
     lines = [f"{m} {n}"]
     for i in range(m):
         c = np.nonzero(H[i])[0]
         lines.append(" ".join([str(len(c))] + [str(x) for x in c]))
-    res = subprocess.run([checker], input="\n".join(lines) + "\n", capture_output=True, text=True, timeout=120)
+    res = subprocess.run([checker] + [str(x) for x in geometry], input="\n".join(lines) + "\n", capture_output=True, text=True, timeout=120)
     assert res.returncode == 0 and res.stdout.startswith("ok"), res.stdout + res.stderr
     return float(res.stdout.split()[1])
 
@@ -53,3 +53,32 @@ def test_layout_other_degrees(checker):
 
 def test_layout_paper_example(checker):
     run(checker, wl.paper_tanner_example())
+
+
+# (rows per thread, bits per thread, bit-side stride) of the layout variants
+# for the eight QC codes (one row degree, columns of degree 2, 3 and 6 or 4)
+QC_GEOMETRY = {6: [(2, 4, 6), (1, 2, 6)], 9: [(2, 6, 6)], 12: [(1, 4, 6)], 16: [(1, 6, 4)]}
+
+
+@pytest.mark.parametrize("k", range(8))
+def test_layout_qc_family_padded_columns(checker, k):
+    c = wl.qc_multi_code_family(seed=7)[k]
+    H = c["H"]
+    dc = int(H.sum(axis=1).max())
+    assert int(H.sum(axis=1).min()) == dc
+    done = 0
+    for rpt, cpt, dvs in QC_GEOMETRY[dc]:
+        m, n = H.shape
+        nt = max(-(-m // rpt), -(-n // cpt))
+        if -(-nt // 64) * 64 > 512:
+            continue
+        load = run(checker, H, (rpt, cpt, dvs))
+        assert load <= 2.0
+        done += 1
+    assert done >= 1
+
+
+def test_layout_stride_above_degree(checker):
+    # a (3,6) code laid out with room for six messages per bit: three zero entries each
+    run(checker, wl.regular_ldpc(512, 256, 3, 6, seed=9), (2, 4, 6))
+    run(checker, wl.regular_ldpc(512, 256, 3, 6, seed=9), (1, 2, 3))
