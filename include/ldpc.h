@@ -221,8 +221,11 @@ size_t ldpc_multi_workspace_bytes(int32_t njobs);
  * launch shape (the same graph, or graphs of one shape); the others share one
  * persistent launch.  In each launch workgroups take frames from per-job
  * counters, largest job (frames x edges) first, and move to the next job
- * without waiting for the others.  All launches are enqueued on `stream` in
- * this call.
+ * without waiting for the others.  Several launches run side by side: the
+ * first on `stream`, the others on side streams that the library creates
+ * once per device (default priority) and forks from `stream` and joins back
+ * into it in this call, so that the call is ordered on `stream` like one
+ * kernel.  Calls on one device take a lock while they enqueue.
  * Errors: LDPC_EINVAL (null or empty job list, null pointers in a job with
  * B > 0, B < 0, max_iter < 0), LDPC_EUNSUPPORTED (a graph does not fit, or
  * more than LDPC_MAX_JOBS jobs), LDPC_EWORKSPACE, LDPC_EHIP.

@@ -2,6 +2,8 @@
 // single-graph and multi-graph launches.  The kernels are in onchip_kernel.h
 // (one instantiation per source file and register budget).
 #include <algorithm>
+#include <mutex>
+#include <new>
 
 #include "onchip_kernel.h"
 
@@ -142,6 +144,38 @@ int launch_grid(const void *fn, int threads, size_t lds, int num_cu, int64_t fra
     *grid = (int)(want < groups ? want : groups);
     if (*grid < 1) *grid = 1;
     return LDPC_OK;
+}
+
+// Side streams of the multi-code decoder, one set per device, created on
+// first use (default priority, non-blocking) and kept until the process
+// ends; `mu` serialises the calls that fork onto them.
+constexpr int kSideStreams = 3;
+struct SideStreams {
+    hipStream_t s[kSideStreams];
+    hipEvent_t fork, join[kSideStreams];
+    std::mutex mu;
+};
+SideStreams *side_streams() {
+    constexpr int kMaxDevices = 64;
+    static SideStreams *sets[kMaxDevices] = {};
+    static bool failed[kMaxDevices] = {};
+    static std::mutex make;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(make);
+    if (!sets[dev] && !failed[dev]) {
+        failed[dev] = true; // until the set is complete
+        SideStreams *x = new (std::nothrow) SideStreams();
+        if (!x) return nullptr;
+        bool ok = hipEventCreateWithFlags(&x->fork, hipEventDisableTiming) == hipSuccess;
+        for (int k = 0; k < kSideStreams && ok; ++k)
+            ok = hipStreamCreateWithFlags(&x->s[k], hipStreamNonBlocking) == hipSuccess &&
+                 hipEventCreateWithFlags(&x->join[k], hipEventDisableTiming) == hipSuccess;
+        if (!ok) return nullptr; // (a partial set is left to the process end; every call runs on `stream`)
+        sets[dev] = x;
+        failed[dev] = false;
+    }
+    return sets[dev];
 }
 
 } // namespace
@@ -311,6 +345,13 @@ int onchip_decode_multi(const ldpc_job *jobs, int32_t njobs, int32_t L, uint32_t
     // LDS size and workgroup cap (the same graph, or graphs of one shape) go
     // into one launch of it, in order (largest first), so that each job's last
     // frames overlap the next job's first ones.
+    struct Launch {
+        KernelFn fn;
+        int grid, threads;
+        size_t lds;
+        JobTable jt;
+    };
+    std::vector<Launch> launches;
     std::vector<bool> placed(own.size(), false);
     for (size_t a = 0; a < own.size(); ++a) {
         if (placed[a]) continue;
@@ -332,13 +373,36 @@ int onchip_decode_multi(const ldpc_job *jobs, int32_t njobs, int32_t L, uint32_t
         const int st = launch_grid((const void *)own[a].fn, t, l, own[a].num_cu, fr, own[a].wg_per_cu, &grid,
                                    kVariants[own[a].J.variant].f);
         if (st) return st;
-        timed_launch(K_ONCHIP, own[a].fn, grid, t, l, stream, ot, L, early);
+        launches.push_back(Launch{own[a].fn, grid, t, l, ot});
     }
     if (frames > 0) {
         int grid = 0;
         const int st = launch_grid((const void *)k_onchip_multi, threads, lds, num_cu, frames, 0, &grid);
         if (st) return st;
-        timed_launch(K_ONCHIP, k_onchip_multi, grid, threads, lds, stream, jt, L, early);
+        launches.push_back(Launch{k_onchip_multi, grid, threads, lds, jt});
+    }
+    // Several launches run side by side: all but the first go round-robin to
+    // the library's side streams of the device, which wait for everything
+    // enqueued on `stream` so far and which `stream` waits for at the end.
+    // Each launch's last frames (and the shared launch of small jobs) then
+    // overlap the others instead of leaving CUs idle.
+    SideStreams *side = launches.size() > 1 ? side_streams() : nullptr;
+    std::unique_lock<std::mutex> hold;
+    if (side) {
+        hold = std::unique_lock<std::mutex>(side->mu);
+        LDPC_HIP_TRY(hipEventRecord(side->fork, stream));
+        for (int k = 0; k < kSideStreams; ++k) LDPC_HIP_TRY(hipStreamWaitEvent(side->s[k], side->fork, 0));
+    }
+    for (size_t k = 0; k < launches.size(); ++k) {
+        const Launch &x = launches[k];
+        const hipStream_t on = (side && k % (kSideStreams + 1) != 0) ? side->s[k % (kSideStreams + 1) - 1] : stream;
+        timed_launch(K_ONCHIP, x.fn, x.grid, x.threads, x.lds, on, x.jt, L, early);
+    }
+    if (side) {
+        for (int k = 0; k < kSideStreams; ++k) {
+            LDPC_HIP_TRY(hipEventRecord(side->join[k], side->s[k]));
+            LDPC_HIP_TRY(hipStreamWaitEvent(stream, side->join[k], 0));
+        }
     }
     return hipGetLastError() == hipSuccess ? LDPC_OK : LDPC_EHIP;
 }

@@ -593,11 +593,16 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
 
         // ---- bit pass -------------------------------------------------------------
         // As in the check pass: when the registers allow, the messages of all
-        // own bits are read before the first s is written.  Bits past n read
-        // a valid slot (bit 0's, or the padding slot) and write nothing.
-        // CF: each message at its own position (ba), in ascending check order.
-        V evp[CPT][DV];
+        // own bits are read before the first s is written; otherwise those of
+        // the next own bit are read before this bit's s is written (the
+        // compiler cannot move a read of a message above an LDS write it
+        // cannot tell apart from it), so each bit's reads overlap the previous
+        // bit's sum.  Every own slot reads valid addresses (the layout's
+        // tables cover all slots; otherwise bits past n read bit 0's or the
+        // padding slot); only bits below n write s.  CF: each message at its
+        // own position (ba), in ascending check order.
         if constexpr (kPrefetchEta) {
+            V evp[CPT][DV];
 #pragma unroll
             for (int c = 0; c < CPT; ++c) {
                 const int32_t j = tid + c * nt;
@@ -609,26 +614,46 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
                     evp[c][k] = kLay ? lds_ld<V>(lds, ba[kLay ? c : 0][kLay ? k : 0])
                                    : lds_ld<V>(lds, base + kEnt * (uint32_t)(CX || k < dv ? k : 0));
             }
-        }
 #pragma unroll
-        for (int c = 0; c < CPT; ++c) {
-            const int32_t j = tid + c * nt;
-            if (j < n) {
-                // CX: every bit has DV slots, so bit j's first slot is DV j
+            for (int c = 0; c < CPT; ++c) {
+                const int32_t j = tid + c * nt;
+                if (j < n) {
+                    const int32_t dv = CX ? DV : (int32_t)(ckd[c] >> 16);
+                    V acc = (CX || 0 < dv) ? evp[c][0] : vzero<V>();
+#pragma unroll
+                    for (int k = 1; k < DV; ++k)
+                        acc = acc + ((CX || k < dv) ? evp[c][k] : vzero<V>()); // +0 adds change no s
+                    lds_st<V>(lds, kEnt * (uint32_t)j, acc + rc[c]);
+                }
+            }
+        } else {
+            auto bit_msgs = [&](int c, V(&ev)[DV]) {
+                const int32_t j = tid + c * nt;
                 const uint32_t base =
-                    eta0 + kEnt * (CX ? (uint32_t)(DV * j) : (ckd[c] & 0xffffu));
+                    eta0 + kEnt * (CX ? (uint32_t)(DV * (j < n ? j : 0)) : (ckd[c] & 0xffffu));
                 const int32_t dv = CX ? DV : (int32_t)(ckd[c] >> 16);
-                V ev[DV];
 #pragma unroll
                 for (int k = 0; k < DV; ++k)
-                    ev[k] = kPrefetchEta ? evp[c][k]
-                            : kLay       ? lds_ld<V>(lds, ba[kLay ? c : 0][kLay ? k : 0])
-                                         : lds_ld<V>(lds, base + kEnt * (uint32_t)(CX || k < dv ? k : 0));
-                V acc = (CX || 0 < dv) ? ev[0] : vzero<V>();
+                    ev[k] = kLay ? lds_ld<V>(lds, ba[kLay ? c : 0][kLay ? k : 0])
+                                 : lds_ld<V>(lds, base + kEnt * (uint32_t)(CX || k < dv ? k : 0));
+            };
+            V evn[DV];
+            bit_msgs(0, evn);
 #pragma unroll
-                for (int k = 1; k < DV; ++k)
-                    acc = acc + ((CX || k < dv) ? ev[k] : vzero<V>()); // +0 adds change no s
-                lds_st<V>(lds, kEnt * (uint32_t)j, acc + rc[c]);
+            for (int c = 0; c < CPT; ++c) {
+                const int32_t j = tid + c * nt;
+                V ev[DV];
+#pragma unroll
+                for (int k = 0; k < DV; ++k) ev[k] = evn[k];
+                if (c + 1 < CPT) bit_msgs(c + 1, evn);
+                if (j < n) {
+                    const int32_t dv = CX ? DV : (int32_t)(ckd[c] >> 16);
+                    V acc = (CX || 0 < dv) ? ev[0] : vzero<V>();
+#pragma unroll
+                    for (int k = 1; k < DV; ++k)
+                        acc = acc + ((CX || k < dv) ? ev[k] : vzero<V>()); // +0 adds change no s
+                    lds_st<V>(lds, kEnt * (uint32_t)j, acc + rc[c]);
+                }
             }
         }
         // Slots refilled this round start their new frame from s = r: their
