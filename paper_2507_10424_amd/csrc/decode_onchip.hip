@@ -19,7 +19,7 @@ using namespace onchip;
 // runs the largest thread count of its jobs.
 constexpr int kWideVariant = 6;
 constexpr bool shared_launch_ok(int v) { return v != kWideVariant && kVariants[v].cf == 0 && v < 16; }
-static_assert(kNumVariants == 32, "k_onchip_multi dispatches variants 0-5 and 7-13");
+static_assert(kNumVariants == 42, "k_onchip_multi dispatches variants 0-5 and 7-13");
 
 __global__ __launch_bounds__(kMaxThreads) void k_onchip_multi(const JobTable jt, int32_t L, int32_t early) {
     extern __shared__ __attribute__((aligned(16))) unsigned char lds[];
@@ -67,7 +67,7 @@ bool variant_ok(const ldpc_graph &g, int k) {
     const bool cols_ok = (v.cx && !(v.cf & 4)) ? (g.dv_min == v.dv && g.dv_max == v.dv) : g.dv_max <= v.dv;
     // the layout's tables are for their own geometry, stride and thread count
     const bool cf_ok = v.cf == 0 || (g.cf.edge != nullptr && g.cf.rpt == v.rpt && g.cf.cpt == v.cpt &&
-                                     g.cf.dvs == v.dv && threads_for(g, v) == g.cf.nt);
+                                     g.cf.dvs == v.dv && g.cf.dvp == v.dvp && threads_for(g, v) == g.cf.nt);
     const size_t state = v.cf != 0 ? cf_state_bytes(g) : state_bytes(g, v.f);
     return rows_ok && cols_ok && cf_ok && threads_for(g, v) <= kMaxThreads && g.edge_tab != nullptr &&
            state + sizeof(Shared) + 1024 <= (size_t)g.lds_max;
@@ -81,8 +81,8 @@ size_t lds_of(const ldpc_graph &g, int variant) { return state_of(g, variant) + 
 // Default preference when nothing is tuned: the bank-conflict-free layout,
 // then exact degrees, a column mask of 6 before one of 8, two frame slots
 // before four.
-constexpr int kPickOrder[] = {15, 14, 22, 23, 24, 25, 26, 27, 28, 29, 30, 31, 0,  7,  10, 1,
-                              11, 2,  12, 3,  13, 4,  5,  6,  8,  9,  16, 17, 18, 19, 20, 21};
+constexpr int kPickOrder[] = {15, 14, 33, 32, 35, 34, 37, 36, 39, 38, 41, 40, 22, 23, 24, 25, 26, 27, 28, 29, 30,
+                              31, 0,  7,  10, 1,  11, 2,  12, 3,  13, 4,  5,  6,  8,  9,  16, 17, 18, 19, 20, 21};
 static_assert(sizeof(kPickOrder) / sizeof(kPickOrder[0]) == kNumVariants, "every variant has a place");
 
 // The tuned variant if one is set and valid, else the first that fits.
@@ -180,12 +180,16 @@ SideStreams *side_streams() {
 
 } // namespace
 
-bool onchip_cf_geometry(const ldpc_graph &g, int32_t *rpt, int32_t *cpt, int32_t *dvs) {
-    // Among the layout variants for the graph's row degree and a stride that
-    // holds its columns: the least lane work issued per round (threads round
-    // up to whole wavefronts; a check edge weighs about four bit-side adds),
+bool onchip_cf_geometry(const ldpc_graph &g, const std::vector<int32_t> &col_deg, int32_t *rpt, int32_t *cpt,
+                        int32_t *dvs, uint32_t *dvp) {
+    // Among the layout variants for the graph's row degree whose stride (or
+    // degree profile) holds its columns: the least lane work issued per round
+    // (threads round up to whole wavefronts; a check edge weighs about four
+    // bit-side adds, and a bit slot index reads its profile entry's messages),
     // then the exact stride, then more threads (more wavefronts to hide LDS
     // latency when LDS limits the workgroups per CU).
+    std::vector<int32_t> sorted(col_deg);
+    std::sort(sorted.begin(), sorted.end());
     int best = -1;
     int64_t best_cost = 0;
     for (int k = 0; k < kNumVariants; ++k) {
@@ -194,7 +198,16 @@ bool onchip_cf_geometry(const ldpc_graph &g, int32_t *rpt, int32_t *cpt, int32_t
         if (!(v.cf & 4) && (g.dv_min != v.dv || g.dv_max != v.dv)) continue; // exact columns only
         const int t = threads_for(g, v);
         if (t > kMaxThreads) continue;
-        const int64_t cost = (int64_t)t * (4 * v.rpt * v.dc + v.cpt * v.dv);
+        int64_t reads = (int64_t)v.cpt * v.dv;
+        if (v.dvp != 0u) { // bits in ascending degree: slot index c holds sorted[c t .. c t + t)
+            bool holds = true;
+            for (size_t p = 0; p < sorted.size() && holds; ++p)
+                holds = (int32_t)((v.dvp >> (4 * (p / t))) & 15u) >= sorted[p];
+            if (!holds) continue;
+            reads = 0;
+            for (int c = 0; c < v.cpt; ++c) reads += (v.dvp >> (4 * c)) & 15u;
+        }
+        const int64_t cost = (int64_t)t * (4 * v.rpt * v.dc + reads);
         const Variant *b = best >= 0 ? &kVariants[best] : nullptr;
         if (best < 0 || cost < best_cost ||
             (cost == best_cost && (v.dv < b->dv || (v.dv == b->dv && t > threads_for(g, *b))))) {
@@ -206,6 +219,7 @@ bool onchip_cf_geometry(const ldpc_graph &g, int32_t *rpt, int32_t *cpt, int32_t
     *rpt = kVariants[best].rpt;
     *cpt = kVariants[best].cpt;
     *dvs = kVariants[best].dv;
+    *dvp = kVariants[best].dvp;
     return true;
 }
 

@@ -171,6 +171,7 @@ void free_graph_arrays(ldpc_graph *g) {
     g->cf.slot_bit = g->cf.row_class = nullptr;
     g->cf.nt = g->cf.npos = 0;
     g->cf.rpt = g->cf.cpt = g->cf.dvs = 0;
+    g->cf.dvp = 0;
     g->row_ptr = g->col_idx = g->col_ptr = g->csc_edge = g->row_class = g->edge_pos = nullptr;
     g->edge_tab = nullptr;
     g->dense_h = nullptr;
@@ -303,8 +304,9 @@ int build(const uint8_t *H, int32_t m, int32_t n, hipStream_t s, ldpc_graph *g) 
             // geometry of the layout variants that fits the graph best
             ldpc::OnchipLayout lay;
             int32_t rpt = 0, cpt = 0, dvs = 0;
-            if (E > 0 && g->dc_min == g->dc_max && ldpc::onchip_cf_geometry(*g, &rpt, &cpt, &dvs) &&
-                ldpc::onchip_cf_layout(h_rowptr, h_bit, h_class, m, n, rpt, cpt, dvs, &lay)) {
+            uint32_t dvp = 0;
+            if (E > 0 && g->dc_min == g->dc_max && ldpc::onchip_cf_geometry(*g, h_col, &rpt, &cpt, &dvs, &dvp) &&
+                ldpc::onchip_cf_layout(h_rowptr, h_bit, h_class, m, n, rpt, cpt, dvs, dvp, &lay)) {
                 const size_t S = (size_t)lay.rpt * lay.nt;
                 if (dalloc(&g->cf.edge, lay.edge.size()) != hipSuccess ||
                     dalloc(&g->cf.bitpos, lay.bitpos.size()) != hipSuccess ||
@@ -329,6 +331,7 @@ int build(const uint8_t *H, int32_t m, int32_t n, hipStream_t s, ldpc_graph *g) 
                 g->cf.rpt = lay.rpt;
                 g->cf.cpt = lay.cpt;
                 g->cf.dvs = lay.dv;
+                g->cf.dvp = lay.dvp;
             }
         }
     } while (false);

@@ -19,7 +19,10 @@
 //   * and a free LDS position for every edge's message,
 // so that every message read and write is conflict-free and the posterior
 // gathers nearly so.  Bits move only inside their 64-slot block (so frame I/O
-// stays coalesced).  Columns of lower degree than the table's stride, and bit
+// stays coalesced), or, with a column degree profile, are placed in ascending
+// degree (bit slot index c then holds bits of degree at most the profile's
+// entry c, and the kernel reads that many messages for it) and move only
+// among the slots of their own degree.  Columns of lower degree than the table's stride, and bit
 // slots past n, read zero messages from positions that nothing writes: their
 // bit sums then take the same instructions as the others and stay exact.
 //
@@ -102,7 +105,7 @@ std::vector<int32_t> bipartite_edge_colour(int32_t nleft, int32_t nright, const 
 
 bool onchip_cf_layout(const std::vector<int32_t> &rowptr, const std::vector<int32_t> &col,
                       const std::vector<int32_t> &row_class, int32_t m, int32_t n, int32_t rpt, int32_t cpt,
-                      int32_t dvs, OnchipLayout *out) {
+                      int32_t dvs, uint32_t dvp, OnchipLayout *out) {
         const int64_t E = (int64_t)col.size();
     if (m < 1 || n < 1 || E < 1 || n >= 65536 || E >= 65536 || rpt < 1 || cpt < 1) return false;
     int32_t dc = 0;
@@ -119,8 +122,10 @@ bool onchip_cf_layout(const std::vector<int32_t> &rowptr, const std::vector<int3
     auto group_of = [&](int32_t s) { return (s / nt) * (nt / 32) + (s % nt) / 32; };
 
     // ---- 1. rows into slots 0 .. m-1 and bits into slots of their own 64-slot
-    // block, evening out each half-group's classes (bit slot modulo 32) by
-    // local search on the sum of squared (half-group, class) counts
+    // block (with a degree profile: bits in ascending degree, then moves
+    // among the slots of one degree), evening out each half-group's classes
+    // (bit slot modulo 32) by local search on the sum of squared (half-group,
+    // class) counts
     std::vector<int32_t> slot_row(m), row_slot(m);
     std::iota(slot_row.begin(), slot_row.end(), 0);
     std::iota(row_slot.begin(), row_slot.end(), 0);
@@ -129,6 +134,22 @@ bool onchip_cf_layout(const std::vector<int32_t> &rowptr, const std::vector<int3
     for (int32_t j = 0; j < n; ++j) {
         bit_slot[j] = j;
         slot_bit[j] = j;
+    }
+    // with a profile: [lo, hi) of the slots that hold bits of slot p's degree
+    std::vector<int32_t> grp_lo, grp_hi;
+    if (dvp != 0u) {
+        std::stable_sort(slot_bit.begin(), slot_bit.begin() + n,
+                         [&](int32_t a, int32_t b) { return cdeg[a] < cdeg[b]; });
+        grp_lo.assign(n, 0);
+        grp_hi.assign(n, 0);
+        for (int32_t p = 0; p < n; ++p) {
+            const int32_t j = slot_bit[p];
+            bit_slot[j] = p;
+            if ((int32_t)((dvp >> (4 * (p / nt))) & 15u) < cdeg[j]) return false; // the profile does not hold it
+            grp_lo[p] = (p > 0 && cdeg[slot_bit[p - 1]] == cdeg[j]) ? grp_lo[p - 1] : p;
+        }
+        for (int32_t p = n - 1; p >= 0; --p)
+            grp_hi[p] = (p + 1 < n && cdeg[slot_bit[p + 1]] == cdeg[slot_bit[p]]) ? grp_hi[p + 1] : p + 1;
     }
     std::vector<std::vector<int32_t>> rows_of(n);
     for (int32_t i = 0; i < m; ++i)
@@ -178,10 +199,15 @@ bool onchip_cf_layout(const std::vector<int32_t> &rowptr, const std::vector<int3
             }
         } else {
             // slots below n only, so that slots n .. are the empty ones
-            const int32_t b = (int32_t)(rng() % (uint64_t)nblk);
-            const int32_t w = std::min<int32_t>(64, n - 64 * b);
-            p1 = 64 * b + (int32_t)(rng() % (uint64_t)w);
-            p2 = 64 * b + (int32_t)(rng() % (uint64_t)w);
+            if (dvp != 0u) {
+                p1 = (int32_t)(rng() % (uint64_t)n);
+                p2 = grp_lo[p1] + (int32_t)(rng() % (uint64_t)(grp_hi[p1] - grp_lo[p1]));
+            } else {
+                const int32_t b = (int32_t)(rng() % (uint64_t)nblk);
+                const int32_t w = std::min<int32_t>(64, n - 64 * b);
+                p1 = 64 * b + (int32_t)(rng() % (uint64_t)w);
+                p2 = 64 * b + (int32_t)(rng() % (uint64_t)w);
+            }
             if (p1 % 32 == p2 % 32) continue;
             j1 = slot_bit[p1];
             j2 = slot_bit[p2];
@@ -353,6 +379,7 @@ bool onchip_cf_layout(const std::vector<int32_t> &rowptr, const std::vector<int3
     out->nt = nt;
     out->rpt = rpt;
     out->cpt = cpt;
+    out->dvp = dvp;
     out->dc = dc;
     out->dv = dvs;
     out->npos = npos;

@@ -41,6 +41,7 @@ struct ldpc_graph {
         int32_t *row_class = nullptr; // [row slot]: degree class
         int32_t nt = 0, npos = 0;     // threads of its geometry, message positions
         int32_t rpt = 0, cpt = 0, dvs = 0; // rows and bits per thread, bit-side stride
+        uint32_t dvp = 0;                  // column degree profile, 0 none
     } cf;
     // Device copy of the dense m x n H (0/1 bytes) for the dense map-reduce
     // decoder, kept when m * n <= kDenseMaxBytes; null otherwise.
@@ -97,6 +98,7 @@ int onchip_decode(const ldpc_graph &g, const float *llr, int32_t B, int32_t L, u
 struct OnchipLayout {
     int32_t nt = 0;         // threads
     int32_t rpt = 0, cpt = 0; // rows / bits per thread
+    uint32_t dvp = 0;         // column degree profile (4 bits per bit slot index), 0 none
     int32_t dc = 0, dv = 0; // largest row degree, bit-side stride
     int32_t npos = 0;       // message positions (the last one for rows past m)
     std::vector<uint32_t> edge;      // [row slot][k]: bit slot | message position << 16
@@ -106,10 +108,12 @@ struct OnchipLayout {
 };
 bool onchip_cf_layout(const std::vector<int32_t> &rowptr, const std::vector<int32_t> &col,
                       const std::vector<int32_t> &row_class, int32_t m, int32_t n, int32_t rpt, int32_t cpt,
-                      int32_t dvs, OnchipLayout *out);
+                      int32_t dvs, uint32_t dvp, OnchipLayout *out);
 // The layout geometry the on-chip variants offer for a graph (rows of one
-// degree): rows and bits per thread and bit-side stride; false if none fits.
-bool onchip_cf_geometry(const ldpc_graph &g, int32_t *rpt, int32_t *cpt, int32_t *dvs);
+// degree): rows and bits per thread, bit-side stride and column degree
+// profile; false if none fits.
+bool onchip_cf_geometry(const ldpc_graph &g, const std::vector<int32_t> &col_deg, int32_t *rpt, int32_t *cpt,
+                        int32_t *dvs, uint32_t *dvp);
 
 // Several graphs in one on-chip launch.
 size_t onchip_multi_workspace_bytes(int32_t njobs);

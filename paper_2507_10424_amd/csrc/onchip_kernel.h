@@ -155,6 +155,18 @@ template <class V> __device__ __forceinline__ V vzero() {
     return z;
 }
 
+// Messages an own bit slot c reads in the bit pass: DV, or with a column
+// degree profile DVP (bits placed in ascending degree, 4 bits per slot
+// index) the largest degree among the bits of slot index c.
+template <uint32_t DVP, int DV> __host__ __device__ constexpr int slot_cap(int c) {
+    return DVP == 0u ? DV : (int)((DVP >> (4 * c)) & 15u);
+}
+template <uint32_t DVP, int DV, int CPT> __host__ __device__ constexpr int cap_sum() {
+    int t = 0;
+    for (int c = 0; c < CPT; ++c) t += slot_cap<DVP, DV>(c);
+    return t;
+}
+
 // One decoding job: a graph, its frames and outputs.
 struct Job {
     const int32_t *row_ptr;
@@ -197,12 +209,14 @@ struct Job {
 // position of its own; needs rows of degree DC, a layout built for this
 // geometry (RPT, CPT) and a bit-side stride of DV (columns of lower degree
 // read zero messages past their degree, so the bit pass is the exact-degree
-// one).  CF & 3 = 1: the check pass reads each edge's previous message back
-// from its position (no registers for them); CF & 3 = 2: it keeps them in
-// registers, as without the layout (a third fewer LDS reads).  CF & 4: columns
+// one; with a column degree profile DVP the bits are sorted by degree and own
+// bit slot c reads slot_cap(c) messages).  CF & 3 = 1: the check pass reads
+// each edge's previous message back from its position (no registers for
+// them); CF & 3 = 2: it keeps them in registers, as without the layout (a
+// third fewer LDS reads).  CF & 4: columns
 // padded to DV (else every column has degree DV, and the zero positions are
 // never read by a bit below n).
-template <int DC, bool RX, int DV, bool CX, int RPT, int CPT, int F, bool NMS, int CF>
+template <int DC, bool RX, int DV, bool CX, int RPT, int CPT, int F, bool NMS, int CF, uint32_t DVP = 0u>
 __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t early, unsigned char *lds) {
     constexpr bool kLay = (CF & 3) != 0;     // the layout's tables
     constexpr bool kPrevLds = (CF & 3) == 1; // previous messages read from LDS
@@ -215,7 +229,7 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
     // variants, and the layout with padded columns, need those registers to
     // stay within four waves per SIMD)
     constexpr bool kPrefetchS = RPT > 1 && RPT * DC * F <= 32 && CX && !kPad;
-    constexpr bool kPrefetchEta = CPT > 1 && CPT * DV * F <= 32;
+    constexpr bool kPrefetchEta = CPT > 1 && cap_sum<DVP, DV, CPT>() * F <= 32;
     // keep the channel LLRs of every slot's next frame in registers, read
     // ahead, when that takes at most 8 registers and the column degree is
     // exact (the masked-column variants are the ones near the 128-register
@@ -294,7 +308,8 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
         if constexpr (kLay) {
 #pragma unroll
             for (int u = 0; u < DV; ++u)
-                ba[c][u] = eta0 + kEnt * (kPad || p < n ? J.cf_bitpos[(size_t)p * DV + u] : (uint32_t)(J.cf_npos - 1));
+                if (u < slot_cap<DVP, DV>(c))
+                    ba[c][u] = eta0 + kEnt * (kPad || p < n ? J.cf_bitpos[(size_t)p * DV + u] : (uint32_t)(J.cf_npos - 1));
         }
     }
 
@@ -611,8 +626,9 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
                 const int32_t dv = CX ? DV : (int32_t)(ckd[c] >> 16);
 #pragma unroll
                 for (int k = 0; k < DV; ++k)
-                    evp[c][k] = kLay ? lds_ld<V>(lds, ba[kLay ? c : 0][kLay ? k : 0])
-                                   : lds_ld<V>(lds, base + kEnt * (uint32_t)(CX || k < dv ? k : 0));
+                    if (k < slot_cap<DVP, DV>(c))
+                        evp[c][k] = kLay ? lds_ld<V>(lds, ba[kLay ? c : 0][kLay ? k : 0])
+                                       : lds_ld<V>(lds, base + kEnt * (uint32_t)(CX || k < dv ? k : 0));
             }
 #pragma unroll
             for (int c = 0; c < CPT; ++c) {
@@ -622,7 +638,8 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
                     V acc = (CX || 0 < dv) ? evp[c][0] : vzero<V>();
 #pragma unroll
                     for (int k = 1; k < DV; ++k)
-                        acc = acc + ((CX || k < dv) ? evp[c][k] : vzero<V>()); // +0 adds change no s
+                        if (k < slot_cap<DVP, DV>(c))
+                            acc = acc + ((CX || k < dv) ? evp[c][k] : vzero<V>()); // +0 adds change no s
                     lds_st<V>(lds, kEnt * (uint32_t)j, acc + rc[c]);
                 }
             }
@@ -634,8 +651,9 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
                 const int32_t dv = CX ? DV : (int32_t)(ckd[c] >> 16);
 #pragma unroll
                 for (int k = 0; k < DV; ++k)
-                    ev[k] = kLay ? lds_ld<V>(lds, ba[kLay ? c : 0][kLay ? k : 0])
-                                 : lds_ld<V>(lds, base + kEnt * (uint32_t)(CX || k < dv ? k : 0));
+                    if (k < slot_cap<DVP, DV>(c))
+                        ev[k] = kLay ? lds_ld<V>(lds, ba[kLay ? c : 0][kLay ? k : 0])
+                                     : lds_ld<V>(lds, base + kEnt * (uint32_t)(CX || k < dv ? k : 0));
             };
             V evn[DV];
             bit_msgs(0, evn);
@@ -651,7 +669,8 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
                     V acc = (CX || 0 < dv) ? ev[0] : vzero<V>();
 #pragma unroll
                     for (int k = 1; k < DV; ++k)
-                        acc = acc + ((CX || k < dv) ? ev[k] : vzero<V>()); // +0 adds change no s
+                        if (k < slot_cap<DVP, DV>(c))
+                            acc = acc + ((CX || k < dv) ? ev[k] : vzero<V>()); // +0 adds change no s
                     lds_st<V>(lds, kEnt * (uint32_t)j, acc + rc[c]);
                 }
             }
@@ -675,7 +694,8 @@ __device__ __forceinline__ void run_onchip(const Job &J, int32_t L, int32_t earl
                             if constexpr (kPrevLds) { // the new frame's first iteration reads 0 messages
 #pragma unroll
                                 for (int u = 0; u < DV; ++u)
-                                    lds_st<float>(lds, ba[kLay ? c : 0][kLay ? u : 0] + 4u * (uint32_t)q, 0.0f);
+                                    if (u < slot_cap<DVP, DV>(c))
+                                        lds_st<float>(lds, ba[kLay ? c : 0][kLay ? u : 0] + 4u * (uint32_t)q, 0.0f);
                             }
                         }
                     }
@@ -698,6 +718,7 @@ struct Variant {
     int f;  // frame slots per workgroup
     int cf; // the graph's bank-conflict-free layout: 0 no, 1 previous messages in LDS, 2 in registers,
             // + 4 columns of degree below dv padded
+    uint32_t dvp; // layout with bits sorted by degree: messages read per own bit slot c (4 bits each), 0 dv
 };
 
 // Exact-degree variants for the regular codes in use first, then masked ones,
@@ -726,13 +747,22 @@ constexpr Variant kVariants[] = {
     {6, true, 6, true, 1, 2, 2, 6},  {9, true, 6, true, 2, 6, 2, 5},  {9, true, 6, true, 2, 6, 2, 6},
     {12, true, 6, true, 1, 4, 2, 5}, {12, true, 6, true, 1, 4, 2, 6}, {16, true, 4, true, 1, 6, 2, 5},
     {16, true, 4, true, 1, 6, 2, 6},
+    // the same shapes with bits placed in ascending column degree: each bit
+    // slot index reads only as many messages as its bits' largest degree
+    // (profiles of codes whose bits have degrees 2, 3 and 6 or 4 in the
+    // proportions 3:2:1)
+    {6, true, 6, true, 2, 4, 2, 5, 0x6332u},      {6, true, 6, true, 2, 4, 2, 6, 0x6332u},
+    {6, true, 6, true, 1, 2, 2, 5, 0x63u},        {6, true, 6, true, 1, 2, 2, 6, 0x63u},
+    {9, true, 6, true, 2, 6, 2, 5, 0x633222u},    {9, true, 6, true, 2, 6, 2, 6, 0x633222u},
+    {12, true, 6, true, 1, 4, 2, 5, 0x6332u},     {12, true, 6, true, 1, 4, 2, 6, 0x6332u},
+    {16, true, 4, true, 1, 6, 2, 5, 0x433222u},   {16, true, 4, true, 1, 6, 2, 6, 0x433222u},
 };
 constexpr int kNumVariants = (int)(sizeof(kVariants) / sizeof(kVariants[0]));
 
 template <int V, bool NMS>
 __device__ __forceinline__ void run_v(const Job &J, int32_t L, int32_t early, unsigned char *lds) {
     constexpr Variant v = kVariants[V];
-    run_onchip<v.dc, v.rx, v.dv, v.cx, v.rpt, v.cpt, v.f, NMS, v.cf>(J, L, early, lds);
+    run_onchip<v.dc, v.rx, v.dv, v.cx, v.rpt, v.cpt, v.f, NMS, v.cf, v.dvp>(J, L, early, lds);
 }
 
 
@@ -769,7 +799,9 @@ using KernelFn = void (*)(const JobTable, int32_t, int32_t);
      &k_onchip<15, W, N>, &k_onchip<16, W, N>, &k_onchip<17, W, N>, &k_onchip<18, W, N>, &k_onchip<19, W, N>,         \
      &k_onchip<20, W, N>, &k_onchip<21, W, N>, &k_onchip<22, W, N>, &k_onchip<23, W, N>, &k_onchip<24, W, N>,         \
      &k_onchip<25, W, N>, &k_onchip<26, W, N>, &k_onchip<27, W, N>, &k_onchip<28, W, N>, &k_onchip<29, W, N>,         \
-     &k_onchip<30, W, N>, &k_onchip<31, W, N>}
+     &k_onchip<30, W, N>, &k_onchip<31, W, N>, &k_onchip<32, W, N>, &k_onchip<33, W, N>, &k_onchip<34, W, N>,         \
+     &k_onchip<35, W, N>, &k_onchip<36, W, N>, &k_onchip<37, W, N>, &k_onchip<38, W, N>, &k_onchip<39, W, N>,         \
+     &k_onchip<40, W, N>, &k_onchip<41, W, N>}
 // The kernels of each register budget (waves per SIMD 0, 4, 3), one source
 // file each: [learned][variant].
 extern const KernelFn kKernelsW0[2][kNumVariants];

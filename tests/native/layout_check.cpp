@@ -1,9 +1,11 @@
 // Checks the on-chip decoder's bank-conflict-free layout (csrc/layout.hip)
 // on one graph read from stdin ("m n" then, per row, its degree and bits),
 // in the geometry given on the command line (rows and bits per thread,
-// bit-side stride; default 2 4 and the largest column degree): every row
-// slot below m holds a distinct row with its own edges, each bit sits in a
-// slot of its own 64-slot block, every message has a position of its own,
+// bit-side stride, column degree profile in hex; default 2 4, the largest
+// column degree, no profile): every row slot below m holds a distinct row
+// with its own edges, each bit sits in a slot of its own 64-slot block (with
+// a profile: in a slot whose profile entry is at least its degree), every
+// message has a position of its own,
 // the bit-side table lists each bit's messages in ascending check order and
 // zero positions past its degree, and no two lanes of a message access
 // conflict on the LDS banks (writes: distinct positions modulo 16 per 16
@@ -40,17 +42,21 @@ int main(int argc, char **argv) {
     const int dmax = *std::max_element(cdeg.begin(), cdeg.end());
     const int rpt = argc > 1 ? std::atoi(argv[1]) : 2, cpt = argc > 2 ? std::atoi(argv[2]) : 4;
     const int dvs = argc > 3 ? std::atoi(argv[3]) : dmax;
+    const uint32_t dvp = argc > 4 ? (uint32_t)std::strtoul(argv[4], nullptr, 16) : 0u;
     ldpc::OnchipLayout L;
-    if (!ldpc::onchip_cf_layout(rowptr, col, rc, m, n, rpt, cpt, dvs, &L)) return fail("no layout");
+    if (!ldpc::onchip_cf_layout(rowptr, col, rc, m, n, rpt, cpt, dvs, dvp, &L)) return fail("no layout");
     const int nt = L.nt, dc = L.dc, dv = L.dv, S = rpt * nt, P = cpt * nt;
     if (L.rpt != rpt || L.cpt != cpt || dv != dvs || S < m || P < n) return fail("geometry");
     if ((int)L.edge.size() != S * dc || (int)L.bitpos.size() != P * dv || (int)L.slot_bit.size() != n)
         return fail("table sizes");
-    // bits: a permutation of 0..n-1 inside 64-slot blocks
+    // messages bit slot p reads: its profile entry, or the stride
+    auto cap = [&](int p) { return dvp ? (int)((dvp >> (4 * (p / nt))) & 15u) : dv; };
+    // bits: a permutation of 0..n-1 inside 64-slot blocks, or into slots whose cap holds them
     std::vector<int> bit_slot(n, -1);
     for (int p = 0; p < n; ++p) {
         const int j = L.slot_bit[p];
-        if (j < 0 || j >= n || bit_slot[j] >= 0 || j / 64 != p / 64) return fail("bit slots");
+        if (j < 0 || j >= n || bit_slot[j] >= 0) return fail("bit slots");
+        if (dvp ? cap(p) < cdeg[j] : j / 64 != p / 64) return fail("bit slots");
         bit_slot[j] = p;
     }
     // rows: slots below m hold distinct rows with exactly their edges
@@ -150,6 +156,7 @@ int main(int argc, char **argv) {
                     int cnt[32] = {0};
                     std::vector<uint32_t> words;
                     for (int l = 32 * h; l < 32 * h + 32; ++l) {
+                        if (u >= cap(c * nt)) continue; // not read
                         const uint32_t v = L.bitpos[(size_t)(c * nt + 64 * w + l) * dv + u];
                         if (std::find(words.begin(), words.end(), v) != words.end()) continue; // same word
                         words.push_back(v);

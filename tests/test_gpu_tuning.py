@@ -28,7 +28,7 @@ def test_all_launch_choices_agree(tdev):
     llr = torch.from_numpy(llr_np).to(dev)
     ref = oracle_decode(H, llr_np, 40)
     tried = 0
-    for v, wpc, wps in itertools.product(range(32), (0, 1, 3), (0, 4)):
+    for v, wpc, wps in itertools.product(range(42), (0, 1, 3), (0, 4)):
         try:
             ldpc.set_tuning(g, 1, variant=v, wg_per_cu=wpc, waves_per_simd=wps)
         except ldpc.LdpcError as e:
@@ -198,7 +198,7 @@ def test_every_variant_on_qc_family(tdev):
         ref_nms = oracle_decode(c["H"], llr_np[:40], T, alpha=alpha, beta=beta)
         al, be = torch.from_numpy(alpha).to(dev), torch.from_numpy(beta).to(dev)
         tried = 0
-        for v, wps in itertools.product(range(32), (0, 4, 3)):
+        for v, wps in itertools.product(range(42), (0, 4, 3)):
             try:
                 ldpc.set_tuning(g, 1, variant=v, waves_per_simd=wps)
             except ldpc.LdpcError as e:

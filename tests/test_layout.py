@@ -78,6 +78,40 @@ def test_layout_qc_family_padded_columns(checker, k):
     assert done >= 1
 
 
+# the same with bits in ascending degree and the profile of messages read per
+# bit slot index (hex, 4 bits per index)
+QC_PROFILE = {6: [(2, 4, 6, "6332"), (1, 2, 6, "63")], 9: [(2, 6, 6, "633222")], 12: [(1, 4, 6, "6332")],
+              16: [(1, 6, 4, "433222")]}
+
+
+@pytest.mark.parametrize("k", [0, 2, 4, 5, 6, 7])
+def test_layout_qc_family_degree_profile(checker, k):
+    c = wl.qc_multi_code_family(seed=7)[k]
+    H = c["H"]
+    m, n = H.shape
+    dc = int(H.sum(axis=1).max())
+    done = 0
+    for rpt, cpt, dvs, prof in QC_PROFILE[dc]:
+        nt = -(-max(-(-m // rpt), -(-n // cpt)) // 64) * 64
+        caps = [int(x, 16) for x in reversed(prof)]
+        deg = np.sort(H.sum(axis=0))
+        if nt > 512 or any(caps[p // nt] < deg[p] for p in range(n)):
+            continue
+        assert run(checker, H, (rpt, cpt, dvs, prof)) <= 2.0
+        done += 1
+    assert done >= 1
+
+
+def test_layout_profile_that_does_not_hold(checker):
+    # a profile of two messages for every slot cannot hold degree-3 bits
+    H = wl.regular_ldpc(512, 256, 3, 6, seed=9)
+    m, n = H.shape
+    lines = [f"{m} {n}"] + [" ".join([str(int(r.sum()))] + [str(x) for x in np.nonzero(r)[0]]) for r in H]
+    res = subprocess.run([checker, "2", "4", "3", "2222"], input="\n".join(lines) + "\n", capture_output=True,
+                         text=True, timeout=60)
+    assert res.stdout.startswith("FAIL no layout")
+
+
 def test_layout_stride_above_degree(checker):
     # a (3,6) code laid out with room for six messages per bit: three zero entries each
     run(checker, wl.regular_ldpc(512, 256, 3, 6, seed=9), (2, 4, 6))
