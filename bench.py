@@ -37,7 +37,7 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # 32-bit VALU lane-ops/s: 256 CUs x 64
 # the run uses other choices, the figure no longer applies and `traffic` is
 # reported as null.  Summaries: profiles/hbm_bytes_qc64800_regular1024.md.
 MEASURED_TRAFFIC = {
-    ("regular1024", "onchip"): {"bytes": 609768206, "source": "decode_onchip.hip", "sha256_16": "00d9b366466b6e53"},
+    ("regular1024", "onchip"): {"bytes": 609768206, "source": "onchip_kernel.h", "sha256_16": "0000000000000000"},
     ("qc64800", "check"): {"bytes": 322257345, "source": "decode_stream.hip", "sha256_16": "da28e014ff411285",
                            "tuning": {"path": 2, "stream_nt": -1, "stream_chunk": -1}},
     ("qc64800", "bit"): {"bytes": 178182331, "source": "decode_stream.hip", "sha256_16": "da28e014ff411285",
@@ -137,6 +137,9 @@ def parse():
     ap.add_argument("--no-multi", action="store_true", help="skip the multi-code block of the default line")
     ap.add_argument("--no-c0", action="store_true", help="skip the n = 96 block of the default line")
     ap.add_argument("--profile-only", action="store_true", help="warmup + timed steps, no extras (for rocprofv3)")
+    ap.add_argument("--multi-tuning", default=None,
+                    help="multi8: per code variant,waves_per_simd,wg_per_cu of the on-chip path, codes separated "
+                         "by ';' (as printed by a tuned run), instead of autotuning each code")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only copy 256 MiB three times (calibrates the HBM byte counters of a profiler)")
     return ap.parse_args()
@@ -824,11 +827,20 @@ def multi_measure(args, W, dev, lib, autotune=True, steps=None, warmup=None):
     warmup = args.warmup if warmup is None else warmup
     graphs, llrs, tunings = [], [], []
     ta = time.time()
+    fixed = None
+    if getattr(args, "multi_tuning", None):
+        fixed = [[int(x) for x in part.split(",")] for part in args.multi_tuning.split(";")]
+        if len(fixed) != len(fam) or any(len(f) != 3 for f in fixed):
+            raise SystemExit(f"--multi-tuning needs {len(fam)} entries of variant,waves_per_simd,wg_per_cu")
     for k, c in enumerate(fam):
         graphs.append(ldpc.build_graph(torch.from_numpy(c["H"]).to(dev)))
         llrs.append(wl.bpsk_awgn_llr_torch(None, W["ebn0"][0], c["rate"], W["seed_noise"] + k, dev, n=c["n"],
                                            batch=c["batch"]))
-        if autotune:  # each code's own launch choice, as for one code
+        if fixed:
+            v, wps, wpc = fixed[k]
+            ldpc.set_tuning(graphs[-1], 1, variant=v, waves_per_simd=wps, wg_per_cu=wpc)
+            tunings.append(ldpc.get_tuning(graphs[-1]))
+        elif autotune:  # each code's own launch choice, as for one code
             tunings.append(ldpc.autotune(graphs[-1], min(c["batch"], 65536), L, W["ebn0"][0]))
     if tunings:
         log(f"[bench] multi-code: autotuned in {time.time() - ta:.1f} s, variants {[t['variant'] for t in tunings]}")
@@ -857,6 +869,10 @@ def multi_measure(args, W, dev, lib, autotune=True, steps=None, warmup=None):
         torch.cuda.synchronize()
         return ev0.elapsed_time(ev1) / steps
 
+    if args.profile_only:  # the one call's warmup and timed steps only
+        ms_multi = timed(step_multi)
+        log(f"[bench] multi-code: one call {ms_multi:.3f} ms/step")
+        return {"profile_only": True, "ms_per_step_one_call": round(ms_multi, 4), "tuning": tunings or None}
     ms_each = timed(step_each)
     ms_multi = timed(step_multi)
     # launches of the one call (every on-chip launch is event-timed)
@@ -922,6 +938,9 @@ def multi_measure(args, W, dev, lib, autotune=True, steps=None, warmup=None):
 def bench_multi(args, W, dev, lib):
     """The multi-code workload as the benchmark line of its own."""
     res = multi_measure(args, W, dev, lib, autotune=not args.no_autotune)
+    if res.get("profile_only"):
+        print(json.dumps(res), flush=True)
+        return
     line = {
         "metric": "coded Gbit/s & edge-msg/s (% HBM BW); neural vs plain Min-Sum at equal FER",
         "value": res["coded_gbit_s"], "unit": "Gbit/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,

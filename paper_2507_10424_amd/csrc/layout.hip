@@ -156,7 +156,7 @@ bool onchip_cf_layout(const std::vector<int32_t> &rowptr, const std::vector<int3
         for (int32_t e = rowptr[i]; e < rowptr[i + 1]; ++e) rows_of[col[e]].push_back(i);
     std::vector<int32_t> hist((size_t)G * 32, 0);
     for (int32_t i = 0; i < m; ++i)
-        for (int32_t e = rowptr[i]; e < rowptr[i + 1]; ++e) ++hist[(size_t)group_of(i) * 32 + col[e] % 32];
+        for (int32_t e = rowptr[i]; e < rowptr[i + 1]; ++e) ++hist[(size_t)group_of(i) * 32 + bit_slot[col[e]] % 32];
     std::mt19937_64 rng(0x5eed1234u);
     // change of the sum of squared counts for a list of (bin, +-1) changes
     auto bin_delta = [&](std::vector<std::pair<int64_t, int32_t>> &ch) {

@@ -73,7 +73,7 @@ def test_layout_qc_family_padded_columns(checker, k):
         if -(-nt // 64) * 64 > 512:
             continue
         load = run(checker, H, (rpt, cpt, dvs))
-        assert load <= 2.0
+        assert load <= 1.25
         done += 1
     assert done >= 1
 
@@ -97,7 +97,9 @@ def test_layout_qc_family_degree_profile(checker, k):
         deg = np.sort(H.sum(axis=0))
         if nt > 512 or any(caps[p // nt] < deg[p] for p in range(n)):
             continue
-        assert run(checker, H, (rpt, cpt, dvs, prof)) <= 2.0
+        # posterior gathers as even as without the profile (a histogram that
+        # started from the unsorted placement once left them near 2)
+        assert run(checker, H, (rpt, cpt, dvs, prof)) <= 1.25
         done += 1
     assert done >= 1
 
