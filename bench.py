@@ -37,7 +37,7 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # 32-bit VALU lane-ops/s: 256 CUs x 64
 # the run uses other choices, the figure no longer applies and `traffic` is
 # reported as null.  Summaries: profiles/hbm_bytes_qc64800_regular1024.md.
 MEASURED_TRAFFIC = {
-    ("regular1024", "onchip"): {"bytes": 609768206, "source": "onchip_kernel.h", "sha256_16": "0000000000000000"},
+    ("regular1024", "onchip"): {"bytes": 609770803, "source": "onchip_kernel.h", "sha256_16": "3d2318242d8c9707"},
     ("qc64800", "check"): {"bytes": 322257345, "source": "decode_stream.hip", "sha256_16": "da28e014ff411285",
                            "tuning": {"path": 2, "stream_nt": -1, "stream_chunk": -1}},
     ("qc64800", "bit"): {"bytes": 178182331, "source": "decode_stream.hip", "sha256_16": "da28e014ff411285",
@@ -843,7 +843,8 @@ def multi_measure(args, W, dev, lib, autotune=True, steps=None, warmup=None):
         elif autotune:  # each code's own launch choice, as for one code
             tunings.append(ldpc.autotune(graphs[-1], min(c["batch"], 65536), L, W["ebn0"][0]))
     if tunings:
-        log(f"[bench] multi-code: autotuned in {time.time() - ta:.1f} s, variants {[t['variant'] for t in tunings]}")
+        how = "tunings from --multi-tuning" if fixed else f"autotuned in {time.time() - ta:.1f} s"
+        log(f"[bench] multi-code: {how}, variants {[t['variant'] for t in tunings]}")
     jobs = list(zip(graphs, llrs))
     outs = [ldpc._outputs(c["batch"], c["n"], dev, True) for c in fam]
     ws = torch.empty(int(lib.ldpc_multi_workspace_bytes(len(jobs))), dtype=torch.uint8, device=dev)

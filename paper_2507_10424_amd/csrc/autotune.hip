@@ -123,10 +123,11 @@ extern "C" int ldpc_autotune(ldpc_graph *g, int32_t B, int32_t max_iter, float e
     std::vector<ldpc_tuning> cands;
     // A kernel that spills under the compiler's own budget stays a candidate
     // only for graphs that no spill-free one fits.  Under a tighter budget
-    // spills are timed like anything else: the compiler tends to put them in
-    // the set-up and refill code, outside the rounds.  A tighter budget is
-    // only tried where it differs from the compiler's (which takes more than
-    // a quarter, or a third, of the 512 registers).
+    // moderate spills are timed like anything else (the compiler tends to put
+    // them in the set-up and refill code, outside the rounds); more than 320
+    // bytes per thread reach into the rounds and are left out.  A tighter
+    // budget is only tried where it differs from the compiler's (which takes
+    // more than a quarter, or a third, of the 512 registers).
     bool clean_fit = false;
     for (int v = 0; v < onchip_num_variants(); ++v)
         clean_fit = clean_fit || (onchip_variant_fits(*g, v) && onchip_kernel_spill_free(v, 0));
@@ -135,6 +136,7 @@ extern "C" int ldpc_autotune(ldpc_graph *g, int32_t B, int32_t max_iter, float e
         const int regs = onchip_kernel_vgprs(v, 0);
         for (int wps : {0, 4, 3}) {
             if (wps == 0 && !onchip_kernel_spill_free(v, 0) && clean_fit) continue;
+            if (wps != 0 && onchip_kernel_spill_bytes(v, wps) > 320) continue;
             if (wps == 4 && regs >= 0 && regs <= 128) continue;
             if (wps == 3 && regs >= 0 && regs <= 168) continue;
             for (int wpc : {0, 1, 2, 3, 4}) cands.push_back(ldpc_tuning{1, v, wpc, 4, wps, 0.0f, -1, -1});

@@ -229,12 +229,14 @@ bool onchip_variant_fits(const ldpc_graph &g, int variant) { return variant_ok(g
 
 int onchip_num_variants() { return kNumVariants; }
 
-bool onchip_kernel_spill_free(int variant, int waves_per_simd) {
-    if (variant < 0 || variant >= kNumVariants) return false;
+bool onchip_kernel_spill_free(int variant, int waves_per_simd) { return onchip_kernel_spill_bytes(variant, waves_per_simd) == 0; }
+
+int64_t onchip_kernel_spill_bytes(int variant, int waves_per_simd) {
+    if (variant < 0 || variant >= kNumVariants) return -1;
     hipFuncAttributes a{};
     if (hipFuncGetAttributes(&a, (const void *)kKernels[budget_index(waves_per_simd)][0][variant]) != hipSuccess)
-        return false;
-    return a.localSizeBytes == 0;
+        return -1;
+    return (int64_t)a.localSizeBytes;
 }
 
 int onchip_kernel_vgprs(int variant, int waves_per_simd) {

@@ -83,6 +83,8 @@ bool onchip_variant_fits(const ldpc_graph &g, int variant);
 int onchip_num_variants();
 // Whether the kernel of (variant, register budget) needs no scratch (no spills).
 bool onchip_kernel_spill_free(int variant, int waves_per_simd);
+// Scratch bytes per thread of that kernel (register spills), -1 if unknown.
+int64_t onchip_kernel_spill_bytes(int variant, int waves_per_simd);
 // Vector registers per thread of that kernel (-1 if unknown).
 int onchip_kernel_vgprs(int variant, int waves_per_simd);
 size_t onchip_workspace_bytes(const ldpc_graph &g, int32_t B);
