@@ -225,7 +225,10 @@ size_t ldpc_multi_workspace_bytes(int32_t njobs);
  * first on `stream`, the others on side streams that the library creates
  * once per device (default priority) and forks from `stream` and joins back
  * into it in this call, so that the call is ordered on `stream` like one
- * kernel.  Calls on one device take a lock while they enqueue.
+ * kernel.  Calls on one device take a lock while they enqueue.  The first
+ * call on a device that needs them creates the side streams: make it before
+ * capturing such a call into a HIP graph (a capture records the fork and the
+ * join as graph dependencies).
  * Errors: LDPC_EINVAL (null or empty job list, null pointers in a job with
  * B > 0, B < 0, max_iter < 0), LDPC_EUNSUPPORTED (a graph does not fit, or
  * more than LDPC_MAX_JOBS jobs), LDPC_EWORKSPACE, LDPC_EHIP.
