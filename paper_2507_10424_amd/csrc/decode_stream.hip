@@ -219,12 +219,16 @@ __global__ __launch_bounds__(512) void k_check_dc(const int32_t *__restrict__ co
     // flags are tested, so that their latencies overlap; the empty asm, which
     // takes a value that depends on every index, keeps the compiler from
     // moving the index loads behind the test.
+    // the wavefront's rows (a row past m repeats row0, and computes nothing)
+    int32_t rw[RPW];
+#pragma unroll
+    for (int q = 0; q < RPW; ++q) rw[q] = row0 + q < m ? row0 + q : row0;
     int32_t ci[RPW][DC];
     int32_t all = 0;
 #pragma unroll
     for (int q = 0; q < RPW; ++q) {
-        // rows of equal degree: CSR offsets are row * DC; a row past m repeats row0
-        const int64_t e0 = (int64_t)(row0 + q < m ? row0 + q : row0) * DC;
+        // rows of equal degree: CSR offsets are row * DC
+        const int64_t e0 = (int64_t)rw[q] * DC;
 #pragma unroll
         for (int k = 0; k < DC; ++k) ci[q][k] = col_idx[e0 + k];
     }
@@ -241,7 +245,7 @@ __global__ __launch_bounds__(512) void k_check_dc(const int32_t *__restrict__ co
     float sj[RPW][DC], ev[RPW][DC];
 #pragma unroll
     for (int q = 0; q < RPW; ++q) {
-        const int64_t e0 = (int64_t)(row0 + q < m ? row0 + q : row0) * DC;
+        const int64_t e0 = (int64_t)rw[q] * DC;
 #pragma unroll
         for (int k = 0; k < DC; ++k) sj[q][k] = sv[(size_t)ci[q][k] * kTile];
 #pragma unroll
@@ -250,8 +254,8 @@ __global__ __launch_bounds__(512) void k_check_dc(const int32_t *__restrict__ co
     uint32_t syn = 0;
 #pragma unroll
     for (int q = 0; q < RPW; ++q) {
-        const int32_t row = row0 + q;
-        if (row >= m) break;
+        if (row0 + q >= m) break;
+        const int32_t row = rw[q];
         float x[DC], a[DC];
         uint32_t xb[DC], sb[DC];
 #pragma unroll
@@ -532,8 +536,11 @@ int stream_decode(const ldpc_graph &g, const float *llr, int32_t B, int32_t L, u
                                                      : k_check_dc<6, kRowsPerWave, NT, true>)
                                             : (alpha ? k_check_dc<7, kRowsPerWave, NT, false>
                                                      : k_check_dc<7, kRowsPerWave, NT, true>);
-                    timed_launch(K_CHECK, fn, ct * row_blocks_dc, 64 * waves, 0, stream, g.col_idx, g.row_class, g.m,
-                                 g.n, g.E, row_blocks_dc, r, s, eta, done, u[t & 1], t, alpha, beta, ncls);
+                    // the graph's rows in the streaming order where it has one
+                    const int32_t *cidx = g.stream_order.col_idx ? g.stream_order.col_idx : g.col_idx;
+                    const int32_t *rcls = g.stream_order.row_class ? g.stream_order.row_class : g.row_class;
+                    timed_launch(K_CHECK, fn, ct * row_blocks_dc, 64 * waves, 0, stream, cidx, rcls, g.m, g.n, g.E,
+                                 row_blocks_dc, r, s, eta, done, u[t & 1], t, alpha, beta, ncls);
                 } else
                     timed_launch(K_CHECK, k_check<NT>, ct * row_blocks, 64 * waves, 0, stream, g.row_ptr, g.col_idx,
                                  g.row_class, g.m, g.n, g.E, row_blocks, r, s, eta, done, u[t & 1], t, alpha, beta,
@@ -541,8 +548,8 @@ int stream_decode(const ldpc_graph &g, const float *llr, int32_t B, int32_t L, u
                 // is the decision of iteration t - 1 tested?
                 const int32_t test_now = (period > 0 && (t - 1) % period == 0) ? 1 : 0;
                 timed_launch(K_BIT, k_bit<kColsPerWave, NT>, ct * col_blocks, 64 * waves, 0, stream, g.col_ptr,
-                             g.csc_edge, g.n, g.E, col_blocks, r, s, eta, done, u[t & 1], u[(t + 1) & 1], conv, t,
-                             test_now);
+                             (regular && g.stream_order.csc_edge) ? g.stream_order.csc_edge : g.csc_edge, g.n, g.E,
+                             col_blocks, r, s, eta, done, u[t & 1], u[(t + 1) & 1], conv, t, test_now);
             }
         }
     };

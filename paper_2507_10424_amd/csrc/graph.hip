@@ -167,6 +167,10 @@ void free_graph_arrays(ldpc_graph *g) {
     (void)hipFree(g->cf.bitpos);
     (void)hipFree(g->cf.slot_bit);
     (void)hipFree(g->cf.row_class);
+    (void)hipFree(g->stream_order.col_idx);
+    (void)hipFree(g->stream_order.csc_edge);
+    (void)hipFree(g->stream_order.row_class);
+    g->stream_order.col_idx = g->stream_order.csc_edge = g->stream_order.row_class = nullptr;
     g->cf.edge = g->cf.bitpos = nullptr;
     g->cf.slot_bit = g->cf.row_class = nullptr;
     g->cf.nt = g->cf.npos = 0;
@@ -332,6 +336,45 @@ int build(const uint8_t *H, int32_t m, int32_t n, hipStream_t s, ldpc_graph *g) 
                 g->cf.cpt = lay.cpt;
                 g->cf.dvs = lay.dv;
                 g->cf.dvp = lay.dvp;
+            }
+        }
+        // Row order of the streaming path, where its check kernel reads
+        // posteriors with its unrolled form (rows of 6 or 7 edges) and a tile
+        // of them (256 bytes per bit) exceeds an XCD's 4 MB L2.
+        if (E > 0 && g->dc_min == g->dc_max && (g->dc_max == 6 || g->dc_max == 7) && (size_t)n * 256 > ((size_t)4 << 20)) {
+            std::vector<int32_t> h_colidx(E);
+            if (hipMemcpy(h_colidx.data(), g->col_idx, sizeof(int32_t) * E, hipMemcpyDeviceToHost) != hipSuccess) {
+                fail(LDPC_EHIP);
+                break;
+            }
+            std::vector<int32_t> h_csc(E);
+            if (hipMemcpy(h_csc.data(), g->csc_edge, sizeof(int32_t) * E, hipMemcpyDeviceToHost) != hipSuccess) {
+                fail(LDPC_EHIP);
+                break;
+            }
+            const std::vector<int32_t> ord = ldpc::stream_row_order(h_rowptr, h_colidx, m, n);
+            const int32_t dc = g->dc_max;
+            std::vector<int32_t> ncol(E), ncsc(E + 8, 0), nrc(m), old2new(E);
+            for (int32_t p = 0; p < m; ++p) {
+                const int32_t i = ord[p];
+                nrc[p] = h_class[i];
+                for (int32_t k = 0; k < dc; ++k) {
+                    ncol[(size_t)p * dc + k] = h_colidx[(size_t)i * dc + k];
+                    old2new[(size_t)i * dc + k] = p * dc + k;
+                }
+            }
+            for (int64_t q = 0; q < E; ++q) ncsc[q] = old2new[h_csc[q]];
+            if (dalloc(&g->stream_order.col_idx, E) != hipSuccess || dalloc(&g->stream_order.csc_edge, E + 8) != hipSuccess ||
+                dalloc(&g->stream_order.row_class, m) != hipSuccess) {
+                fail(LDPC_ENOMEM);
+                break;
+            }
+            if (hipMemcpy(g->stream_order.col_idx, ncol.data(), sizeof(int32_t) * E, hipMemcpyHostToDevice) != hipSuccess ||
+                hipMemcpy(g->stream_order.csc_edge, ncsc.data(), sizeof(int32_t) * (E + 8), hipMemcpyHostToDevice) !=
+                    hipSuccess ||
+                hipMemcpy(g->stream_order.row_class, nrc.data(), sizeof(int32_t) * m, hipMemcpyHostToDevice) != hipSuccess) {
+                fail(LDPC_EHIP);
+                break;
             }
         }
     } while (false);

@@ -43,6 +43,19 @@ struct ldpc_graph {
         int32_t rpt = 0, cpt = 0, dvs = 0; // rows and bits per thread, bit-side stride
         uint32_t dvp = 0;                  // column degree profile, 0 none
     } cf;
+    // Streaming path, for graphs of one row degree (6 or 7) whose tile of
+    // posteriors exceeds an L2: the rows renumbered in a cache-friendly order
+    // (stream_row_order), so that the check kernel's launch order follows it
+    // and the messages of consecutive rows stay consecutive in memory.  Row p
+    // of the new numbering is row order[p]; its edges are p DC .. p DC + DC - 1
+    // (bits ascending), csc_edge lists every column's edges in ascending
+    // original row (the column-sum order) by their new numbers.  Null when
+    // the graph keeps its own order.
+    struct {
+        int32_t *col_idx = nullptr;   // E
+        int32_t *csc_edge = nullptr;  // E + 8 (8 entries of padding, 0)
+        int32_t *row_class = nullptr; // m
+    } stream_order;
     // Device copy of the dense m x n H (0/1 bytes) for the dense map-reduce
     // decoder, kept when m * n <= kDenseMaxBytes; null otherwise.
     uint8_t *dense_h = nullptr;
@@ -116,6 +129,11 @@ bool onchip_cf_layout(const std::vector<int32_t> &rowptr, const std::vector<int3
 // profile; false if none fits.
 bool onchip_cf_geometry(const ldpc_graph &g, const std::vector<int32_t> &col_deg, int32_t *rpt, int32_t *cpt,
                         int32_t *dvs, uint32_t *dvp);
+
+// Order of the rows for the streaming check kernel (roworder.hip): a
+// permutation of 0 .. m-1 that keeps rows sharing bits close together.
+std::vector<int32_t> stream_row_order(const std::vector<int32_t> &rowptr, const std::vector<int32_t> &col, int32_t m,
+                                      int32_t n);
 
 // Several graphs in one on-chip launch.
 size_t onchip_multi_workspace_bytes(int32_t njobs);
