@@ -149,8 +149,9 @@ int ldpc_minsum_decode(const ldpc_graph *g, const float *llr_dev, int32_t B, int
 /*
  * Largest workspace ldpc_minsum_decode_noalloc can serve from the library's
  * own device memory: 16 MiB per GPU.  The on-chip path needs about 2 KiB for
- * any batch; the streaming path needs 256 (2 n + E) bytes per frame rounded
- * up to tiles of 64 frames, plus 16 bytes per frame.
+ * any batch; the streaming path needs 8 (2 n + E) + 40 bytes per frame (two
+ * copies of its state, for frame compaction), rounded up to tiles of 64
+ * frames.
  */
 #define LDPC_NOALLOC_SCRATCH_BYTES ((size_t)16 << 20)
 

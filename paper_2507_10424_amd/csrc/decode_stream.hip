@@ -41,11 +41,43 @@ constexpr int kWaves = 4;       // wavefronts per workgroup of the transpose ker
 constexpr int kRowsPerWave = 2; // rows per wavefront of the unrolled check kernel
 constexpr int kColsPerWave = 4; // bit columns per wavefront of the bit kernel
 
-struct StreamWs {
+// Per-slot arrays of the state (slot = tile * 64 + lane), in two sets: frame
+// compaction (below) copies the frames still decoding from one set into the
+// other, packed into the first tiles.
+struct Set {
     float *r, *s, *eta;
-    uint32_t *done;     // frame has stopped (or is padding beyond B)
+    uint32_t *done;     // slot's frame has stopped, or the slot is empty
     uint32_t *unsat[2]; // syndrome nonzero, indexed by iteration parity
     int32_t *conv;      // iteration at which the frame stopped, -1 if not
+    int32_t *fid;       // the frame in the slot, -1 for none
+};
+// Per chunk: which set holds its frames, and the last compaction plan.
+struct Ctrl {
+    uint32_t cur;   // set holding the chunk's frames
+    uint32_t go;    // the last plan compacts
+    int32_t active; // frames still decoding at the last plan
+    uint32_t pad;
+};
+// What every streaming kernel of a chunk receives: both sets, offset to the
+// chunk's first tile, and its control words.  Kernels read ctrl->cur once.
+struct Bufs {
+    Set set[2];
+    Ctrl *ctrl;
+};
+// A set's syndrome flags of parity p.  (A select, not an index: indexing
+// the kernel argument's array with a run-time value makes the compiler copy
+// the struct through LDS and turn its pointers into per-lane values.)
+__device__ __forceinline__ uint32_t *unsat_of(const Set &S, int32_t p) { return (p & 1) ? S.unsat[1] : S.unsat[0]; }
+__device__ __forceinline__ Set cur_set(const Bufs &b) {
+    const uint32_t c = __builtin_amdgcn_readfirstlane(b.ctrl->cur);
+    const Set s0 = b.set[0], s1 = b.set[1];
+    return c ? s1 : s0;
+}
+
+struct StreamWs {
+    Set set[2];
+    Ctrl *ctrl;
+    int32_t *base; // compaction: first destination slot of every tile of a chunk
 };
 
 size_t tiles_of(int32_t B) { return (size_t)((B + kTile - 1) / kTile); }
@@ -59,26 +91,50 @@ StreamWs carve(const ldpc_graph &g, int32_t B, void *base, size_t *total) {
         off = align_up(off + bytes, 256);
         return o;
     };
-    const size_t o_r = take(nt * (size_t)g.n * kTile * 4);
-    const size_t o_s = take(nt * (size_t)g.n * kTile * 4);
-    const size_t o_e = take(nt * (size_t)g.E * kTile * 4);
-    const size_t o_d = take(fr * 4);
-    const size_t o_u0 = take(fr * 4);
-    const size_t o_u1 = take(fr * 4);
-    const size_t o_c = take(fr * 4);
+    size_t o_r[2], o_s[2], o_e[2], o_d[2], o_u0[2], o_u1[2], o_c[2], o_f[2];
+    for (int k = 0; k < 2; ++k) {
+        o_r[k] = take(nt * (size_t)g.n * kTile * 4);
+        o_s[k] = take(nt * (size_t)g.n * kTile * 4);
+        o_e[k] = take(nt * (size_t)g.E * kTile * 4);
+        o_d[k] = take(fr * 4);
+        o_u0[k] = take(fr * 4);
+        o_u1[k] = take(fr * 4);
+        o_c[k] = take(fr * 4);
+        o_f[k] = take(fr * 4);
+    }
+    const size_t o_ctrl = take(sizeof(Ctrl));
+    const size_t o_base = take(nt * 4);
     if (total) *total = off;
     StreamWs w{};
     char *b = (char *)base;
     if (b) {
-        w.r = (float *)(b + o_r);
-        w.s = (float *)(b + o_s);
-        w.eta = (float *)(b + o_e);
-        w.done = (uint32_t *)(b + o_d);
-        w.unsat[0] = (uint32_t *)(b + o_u0);
-        w.unsat[1] = (uint32_t *)(b + o_u1);
-        w.conv = (int32_t *)(b + o_c);
+        for (int k = 0; k < 2; ++k) {
+            w.set[k].r = (float *)(b + o_r[k]);
+            w.set[k].s = (float *)(b + o_s[k]);
+            w.set[k].eta = (float *)(b + o_e[k]);
+            w.set[k].done = (uint32_t *)(b + o_d[k]);
+            w.set[k].unsat[0] = (uint32_t *)(b + o_u0[k]);
+            w.set[k].unsat[1] = (uint32_t *)(b + o_u1[k]);
+            w.set[k].conv = (int32_t *)(b + o_c[k]);
+            w.set[k].fid = (int32_t *)(b + o_f[k]);
+        }
+        w.ctrl = (Ctrl *)(b + o_ctrl);
+        w.base = (int32_t *)(b + o_base);
     }
     return w;
+}
+
+// The chunk of tiles c0 .. of both sets.
+Bufs chunk_bufs(const StreamWs &w, const ldpc_graph &g, int32_t c0) {
+    const size_t fo = (size_t)c0 * kTile;
+    Bufs b{};
+    for (int k = 0; k < 2; ++k) {
+        const Set &x = w.set[k];
+        b.set[k] = Set{x.r + fo * g.n, x.s + fo * g.n, x.eta + fo * (size_t)g.E, x.done + fo,
+                       {x.unsat[0] + fo, x.unsat[1] + fo}, x.conv + fo, x.fid + fo};
+    }
+    b.ctrl = w.ctrl;
+    return b;
 }
 
 // Message (eta) accesses, optionally non-temporal: one iteration's messages
@@ -100,6 +156,24 @@ __global__ void k_flags_init(int32_t B, int32_t frames, uint32_t *done, uint32_t
     u0[f] = 0;
     u1[f] = 0;
     conv[f] = -1;
+}
+
+// Set 0 of the streaming decoder: frame f in slot f, nothing stopped.
+__global__ void k_slots_init(int32_t B, int32_t frames, Set S) {
+    const int32_t f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= frames) return;
+    S.done[f] = f >= B;
+    S.unsat[0][f] = 0;
+    S.unsat[1][f] = 0;
+    S.conv[f] = -1;
+    S.fid[f] = f < B ? f : -1;
+}
+
+// A chunk starts in set 0 with no compaction planned.
+__global__ void k_ctrl_reset(Ctrl *ctrl) {
+    ctrl->cur = 0u;
+    ctrl->go = 0u;
+    ctrl->active = 0;
 }
 
 // llr[B][n] -> r[tile][j][64] through a 64 x 64 LDS tile.
@@ -129,11 +203,15 @@ __global__ __launch_bounds__(256) void k_to_tiles(const float *__restrict__ llr,
 template <bool NT>
 __global__ __launch_bounds__(512) void k_check(const int32_t *__restrict__ row_ptr, const int32_t *__restrict__ col_idx,
                                                const int32_t *__restrict__ row_class, int32_t m, int32_t n, int64_t E,
-                                               int32_t row_blocks, const float *__restrict__ r,
-                                               const float *__restrict__ s, float *__restrict__ eta,
-                                               const uint32_t *__restrict__ done, uint32_t *__restrict__ unsat,
-                                               int32_t t, const float *__restrict__ alpha,
-                                               const float *__restrict__ beta, int32_t n_classes) {
+                                               int32_t row_blocks, const Bufs bufs, int32_t t,
+                                               const float *__restrict__ alpha, const float *__restrict__ beta,
+                                               int32_t n_classes) {
+    const Set S = cur_set(bufs);
+    const float *__restrict__ r = S.r;
+    const float *__restrict__ s = S.s;
+    float *__restrict__ eta = S.eta;
+    const uint32_t *__restrict__ done = S.done;
+    uint32_t *__restrict__ unsat = unsat_of(S, t);
     const uint32_t bid = xcd_swizzle(blockIdx.x, gridDim.x);
     const int32_t tile = bid / row_blocks;
     const int32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -202,11 +280,15 @@ __global__ __launch_bounds__(512) void k_check(const int32_t *__restrict__ row_p
 template <int DC, int RPW, bool NT, bool PLAIN>
 __global__ __launch_bounds__(512) void k_check_dc(const int32_t *__restrict__ col_idx,
                                                   const int32_t *__restrict__ row_class, int32_t m, int32_t n,
-                                                  int64_t E, int32_t row_blocks, const float *__restrict__ r,
-                                                  const float *__restrict__ s, float *__restrict__ eta,
-                                                  const uint32_t *__restrict__ done, uint32_t *__restrict__ unsat,
-                                                  int32_t t, const float *__restrict__ alpha,
-                                                  const float *__restrict__ beta, int32_t n_classes) {
+                                                  int64_t E, int32_t row_blocks, const Bufs bufs, int32_t t,
+                                                  const float *__restrict__ alpha, const float *__restrict__ beta,
+                                                  int32_t n_classes) {
+    const Set S = cur_set(bufs);
+    const float *__restrict__ r = S.r;
+    const float *__restrict__ s = S.s;
+    float *__restrict__ eta = S.eta;
+    const uint32_t *__restrict__ done = S.done;
+    uint32_t *__restrict__ unsat = unsat_of(S, t);
     const uint32_t bid = xcd_swizzle(blockIdx.x, gridDim.x);
     const int32_t tile = bid / row_blocks;
     const int32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -300,11 +382,16 @@ __global__ __launch_bounds__(512) void k_check_dc(const int32_t *__restrict__ co
 // in ascending check order from +0, then r is added.
 template <int CPW, bool NT>
 __global__ __launch_bounds__(512) void k_bit(const int32_t *__restrict__ col_ptr, const int32_t *__restrict__ csc_edge,
-                                             int32_t n, int64_t E, int32_t col_blocks, const float *__restrict__ r,
-                                             float *__restrict__ s, const float *__restrict__ eta,
-                                             uint32_t *__restrict__ done, const uint32_t *__restrict__ unsat_cur,
-                                             uint32_t *__restrict__ unsat_next, int32_t *__restrict__ conv, int32_t t,
+                                             int32_t n, int64_t E, int32_t col_blocks, const Bufs bufs, int32_t t,
                                              int32_t test_now) {
+    const Set S = cur_set(bufs);
+    const float *__restrict__ r = S.r;
+    float *__restrict__ s = S.s;
+    const float *__restrict__ eta = S.eta;
+    uint32_t *__restrict__ done = S.done;
+    const uint32_t *__restrict__ unsat_cur = unsat_of(S, t);
+    uint32_t *__restrict__ unsat_next = unsat_of(S, t + 1);
+    int32_t *__restrict__ conv = S.conv;
     const uint32_t bid = xcd_swizzle(blockIdx.x, gridDim.x);
     const int32_t tile = bid / col_blocks;
     const int32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -407,23 +494,81 @@ __global__ __launch_bounds__(512) void k_bit(const int32_t *__restrict__ col_ptr
 // Syndrome of the current decision only (after the last iteration).
 __global__ __launch_bounds__(512) void k_syndrome(const int32_t *__restrict__ row_ptr,
                                                   const int32_t *__restrict__ col_idx, int32_t m, int32_t n,
-                                                  int32_t row_blocks, const float *__restrict__ sv_all,
-                                                  const uint32_t *__restrict__ done, uint32_t *__restrict__ unsat) {
+                                                  int32_t row_blocks, const Bufs bufs, int32_t use_r, int32_t upar) {
+    const Set S = cur_set(bufs);
     const uint32_t bid = xcd_swizzle(blockIdx.x, gridDim.x);
     const int32_t tile = bid / row_blocks;
     const int32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int32_t row = (bid % row_blocks) * (int32_t)(blockDim.x >> 6) + w;
     const int lane = threadIdx.x & 63;
     const int32_t f = tile * kTile + lane;
-    const bool act = !done[f];
+    const bool act = !S.done[f];
     if (row >= m || !__any(act)) return;
-    const float *sv = sv_all + (size_t)tile * n * kTile + lane;
+    const float *sv = (use_r ? S.r : S.s) + (size_t)tile * n * kTile + lane;
     uint32_t syn = 0;
     for (int32_t e = row_ptr[row]; e < row_ptr[row + 1]; ++e) syn ^= sv[(size_t)col_idx[e] * kTile] < 0.0f;
-    if (act && syn) unsat[f] = 1u;
+    if (act && syn) unsat_of(S, upar)[f] = 1u;
 }
 
-// Per frame: iterations and convergence flag.
+// Outputs of the frames in a chunk's slots: iterations and convergence flag
+// per frame (after the last iteration), and (below) posteriors and decisions.
+__global__ void k_out_flags(const Bufs bufs, int32_t slots, int32_t L, int32_t upar, int32_t *__restrict__ iters,
+                            uint8_t *__restrict__ ok) {
+    const Set S = cur_set(bufs);
+    const int32_t f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= slots) return;
+    const int32_t id = S.fid[f];
+    if (id < 0) return;
+    const int32_t c = S.conv[f];
+    iters[id] = c >= 0 ? c : L;
+    if (ok) ok[id] = (c >= 0 || unsat_of(S, upar)[f] == 0u) ? 1 : 0;
+}
+
+// s (or r for frames that stopped at iteration 0) -> post[B][n], bits[B][n]
+// through a 64 x 64 LDS tile.  STOPPED: at a compaction that goes ahead,
+// only the frames that have stopped (they are not copied on), and their
+// iterations and convergence flags too; else, after the last iteration,
+// every frame still in a slot.
+template <bool STOPPED>
+__global__ __launch_bounds__(256) void k_out_tiles(const Bufs bufs, int32_t n, int32_t L, float *__restrict__ post,
+                                                   uint8_t *__restrict__ bits, int32_t *__restrict__ iters,
+                                                   uint8_t *__restrict__ ok) {
+    if (STOPPED && !bufs.ctrl->go) return;
+    const Set S = cur_set(bufs);
+    __shared__ float t[kTile][kTile + 1];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int32_t nchunks = (n + 63) / 64;
+    const int32_t tile = blockIdx.x / nchunks, j0 = (blockIdx.x % nchunks) * 64;
+    const int32_t f_lane = tile * kTile + lane;
+    const int32_t id_lane = S.fid[f_lane];
+    const bool emit = id_lane >= 0 && (!STOPPED || S.done[f_lane]);
+    if (!__syncthreads_or(emit)) return;
+    if (STOPPED && j0 == 0 && w == 0 && emit) { // a stopped frame: it stopped by the codeword test
+        iters[id_lane] = S.conv[f_lane];
+        if (ok) ok[id_lane] = 1;
+    }
+    const bool use_r = L == 0 || S.conv[f_lane] == 0;
+    const float *src = (use_r ? S.r : S.s) + (size_t)tile * n * kTile;
+#pragma unroll 4
+    for (int k = w; k < kTile; k += kWaves) {
+        const int32_t j = j0 + k;
+        t[lane][k] = (j < n) ? src[(size_t)j * kTile + lane] : 0.0f;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int k = w; k < kTile; k += kWaves) {
+        const int32_t fk = tile * kTile + k;
+        const int64_t id = S.fid[fk];
+        const int32_t j = j0 + lane;
+        if (id >= 0 && (!STOPPED || S.done[fk]) && j < n) {
+            const float v = t[k][lane];
+            if (post) post[id * n + j] = v;
+            bits[id * n + j] = v < 0.0f ? 1 : 0;
+        }
+    }
+}
+
+// Dense decoder outputs (frame f in slot f): iterations and convergence flag.
 __global__ void k_finalize(int32_t B, int32_t L, const int32_t *__restrict__ conv,
                            const uint32_t *__restrict__ unsat_final, int32_t *__restrict__ iters,
                            uint8_t *__restrict__ ok) {
@@ -434,7 +579,7 @@ __global__ void k_finalize(int32_t B, int32_t L, const int32_t *__restrict__ con
     if (ok) ok[f] = (c >= 0 || unsat_final[f] == 0u) ? 1 : 0;
 }
 
-// s (or r for frames that stopped at iteration 0) -> post[B][n], bits[B][n].
+// Dense decoder: s (or r for frames that stopped at iteration 0) -> post[B][n], bits[B][n].
 __global__ __launch_bounds__(256) void k_from_tiles(const float *__restrict__ r, const float *__restrict__ s,
                                                     const int32_t *__restrict__ conv, int32_t B, int32_t n,
                                                     int32_t L, float *__restrict__ post, uint8_t *__restrict__ bits) {
@@ -462,6 +607,142 @@ __global__ __launch_bounds__(256) void k_from_tiles(const float *__restrict__ r,
         }
     }
 }
+
+// ---- frame compaction ------------------------------------------------------
+// A 64-frame tile runs until its last frame stops.  Every so often (a fixed
+// schedule of iterations) one workgroup counts the frames still decoding in
+// the chunk; if packing them into fewer tiles frees at least a fifth of the
+// tiles that still run, the frames that have stopped are output, the others
+// are copied into the other set, packed (a tile's frames keep their order
+// and go to consecutive slots, so every store of a row is at most two
+// 256-byte pieces; the packed tiles are spread over the chunk so that every
+// XCD keeps some), the rest of that set's slots are marked empty, and the
+// chunk continues in that set.  Each frame's own
+// arithmetic is unchanged: it sees the same launches in the same order.
+constexpr int kPlanThreads = 1024;
+constexpr int kMoveRows = 128; // rows of r, s and eta per wavefront of the copy
+
+__global__ __launch_bounds__(kPlanThreads) void k_compact_plan(const Bufs bufs, int32_t ct,
+                                                               int32_t *__restrict__ base) {
+    __shared__ int32_t part[kPlanThreads], tiles_on[kPlanThreads];
+    const Set S = cur_set(bufs);
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = kPlanThreads / 64;
+    for (int32_t tile = w; tile < ct; tile += nw) {
+        const uint64_t on = __ballot(S.done[tile * kTile + lane] == 0u);
+        if (lane == 0) base[tile] = __popcll(on);
+    }
+    __syncthreads();
+    // exclusive scan of the per-tile counts: a contiguous segment per thread
+    const int32_t per = (ct + kPlanThreads - 1) / kPlanThreads;
+    const int32_t a0 = tid * per, a1 = a0 + per < ct ? a0 + per : ct;
+    int32_t sum = 0, on = 0;
+    for (int32_t k = a0; k < a1; ++k) {
+        sum += base[k];
+        on += base[k] > 0;
+    }
+    part[tid] = sum;
+    tiles_on[tid] = on;
+    __syncthreads();
+    for (int d = 1; d < kPlanThreads; d <<= 1) { // inclusive Hillis-Steele scan of part, sum of tiles_on
+        const int32_t x = tid >= d ? part[tid - d] : 0;
+        const int32_t y = tid >= d ? tiles_on[tid - d] : 0;
+        __syncthreads();
+        part[tid] += x;
+        tiles_on[tid] += y;
+        __syncthreads();
+    }
+    int32_t run = part[tid] - sum; // exclusive prefix of this segment
+    for (int32_t k = a0; k < a1; ++k) {
+        const int32_t c = base[k];
+        base[k] = run;
+        run += c;
+    }
+    if (tid == 0) {
+        const int32_t active = part[kPlanThreads - 1], t_on = tiles_on[kPlanThreads - 1];
+        const int32_t packed = (active + kTile - 1) / kTile;
+        bufs.ctrl->active = active;
+        bufs.ctrl->go = (t_on - packed >= 1 && 5 * (t_on - packed) >= t_on) ? 1u : 0u;
+    }
+}
+
+// Packed tile k goes to tile spread(k): consecutive packed tiles land in
+// different eighths of the chunk, so that the launches' XCD-contiguous block
+// ranges (xcd_swizzle) keep every XCD busy after a compaction.  A bijection
+// of 0 .. ct-1 (the identity past the largest multiple of 8).
+__device__ __forceinline__ int32_t spread(int32_t k, int32_t ct) {
+    const int32_t stride = ct / 8;
+    return k < 8 * stride ? (k % 8) * stride + k / 8 : k;
+}
+__device__ __forceinline__ int32_t unspread(int32_t p, int32_t ct) {
+    const int32_t stride = ct / 8;
+    return p < 8 * stride ? (p % stride) * 8 + p / stride : p;
+}
+
+// Blocks 0 .. ct * blocks_per_tile - 1 copy the frames still decoding (one
+// source tile per blocks_per_tile blocks); the blocks after them mark the
+// destination slots past the packed frames empty.
+__global__ __launch_bounds__(256) void k_compact_move(const Bufs bufs, const int32_t *__restrict__ base, int32_t n,
+                                                      int64_t E, int32_t ct, int32_t blocks_per_tile) {
+    if (!bufs.ctrl->go) return;
+    const uint32_t c = __builtin_amdgcn_readfirstlane(bufs.ctrl->cur);
+    const Set src = c ? bufs.set[1] : bufs.set[0];
+    const Set dst = c ? bufs.set[0] : bufs.set[1];
+    if ((int32_t)blockIdx.x >= ct * blocks_per_tile) {
+        const int32_t p = ((int32_t)blockIdx.x - ct * blocks_per_tile) * (int32_t)blockDim.x + threadIdx.x;
+        if (p >= ct * kTile) return;
+        if (unspread(p / kTile, ct) * kTile + p % kTile < bufs.ctrl->active) return;
+        dst.done[p] = 1u;
+        dst.unsat[0][p] = 0u;
+        dst.unsat[1][p] = 0u;
+        dst.conv[p] = -1;
+        dst.fid[p] = -1;
+        return;
+    }
+    const int32_t tile = blockIdx.x / blocks_per_tile, wb = blockIdx.x % blocks_per_tile;
+    const int32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int32_t f = tile * kTile + lane;
+    const bool act = src.done[f] == 0u;
+    const uint64_t on = __ballot(act);
+    if (on == 0ull) return;
+    const int32_t k = base[tile] + __popcll(on & ((1ull << lane) - 1ull)); // packed index
+    const int32_t dt = spread(k / kTile, ct), dl = k % kTile;
+    const int32_t ds = dt * kTile + dl; // destination slot
+    if (wb == 0 && w == 0 && act) {
+        dst.done[ds] = 0u;
+        dst.unsat[0][ds] = src.unsat[0][f];
+        dst.unsat[1][ds] = src.unsat[1][f];
+        dst.conv[ds] = src.conv[f];
+        dst.fid[ds] = src.fid[f];
+    }
+    // rows q of [r: n][s: n][eta: E] of this wavefront
+    const int64_t R = 2 * (int64_t)n + E;
+    const int64_t q0 = ((int64_t)wb * (blockDim.x >> 6) + w) * kMoveRows;
+    const int64_t q1 = q0 + kMoveRows < R ? q0 + kMoveRows : R;
+    auto copy = [&](const float *a, float *d, int64_t rows_per_tile, int64_t lo, int64_t hi) {
+        const float *ap = a + (size_t)tile * rows_per_tile * kTile + lane;
+        float *dp = d + (size_t)dt * rows_per_tile * kTile + dl;
+#pragma unroll 8
+        for (int64_t q = lo; q < hi; ++q) {
+            const float v = ap[(size_t)q * kTile];
+            if (act) dp[(size_t)q * kTile] = v;
+        }
+    };
+    if (q0 < n) copy(src.r, dst.r, n, q0, q1 < n ? q1 : n);
+    if (q1 > n && q0 < 2 * (int64_t)n)
+        copy(src.s, dst.s, n, (q0 > n ? q0 : n) - n, (q1 < 2 * (int64_t)n ? q1 : 2 * (int64_t)n) - n);
+    if (q1 > 2 * (int64_t)n) copy(src.eta, dst.eta, E, (q0 > 2 * (int64_t)n ? q0 : 2 * (int64_t)n) - 2 * n, q1 - 2 * n);
+}
+
+__global__ void k_compact_flip(Ctrl *ctrl) {
+    if (ctrl->go) ctrl->cur ^= 1u;
+    ctrl->go = 0u;
+}
+
+// Iterations after which a compaction is planned (roughly geometric: frames
+// stop early at high Eb/N0 and late at low).
+constexpr int32_t kCompactAt[] = {4, 6, 8, 11, 15, 20, 27, 35, 43};
+constexpr int32_t kCompactMinTiles = 16; // chunks of fewer tiles are not compacted
 
 } // namespace
 
@@ -519,17 +800,19 @@ int stream_decode(const ldpc_graph &g, const float *llr, int32_t B, int32_t L, u
                              ? g.tuning.stream_nt == 1
                              : (double)chunk * kTile * 4.0 * (double)g.E > 2.0 * 1024 * 1024 * 1024;
 
-    k_flags_init<<<(frames + 255) / 256, 256, 0, stream>>>(B, frames, w.done, w.unsat[0], w.unsat[1], w.conv);
-    k_to_tiles<<<nt * nchunks, 256, 0, stream>>>(llr, B, g.n, w.r);
+    k_slots_init<<<(frames + 255) / 256, 256, 0, stream>>>(B, frames, w.set[0]);
+    k_to_tiles<<<nt * nchunks, 256, 0, stream>>>(llr, B, g.n, w.set[0].r);
+    // frame compaction needs early exit and chunks large enough to shrink
+    const bool compact = period > 0 && chunk >= kCompactMinTiles;
+    const int32_t move_blocks = (int32_t)((2 * (int64_t)g.n + g.E + 4 * kMoveRows - 1) / (4 * kMoveRows));
     auto iterate = [&](auto nt_tag) {
         constexpr bool NT = decltype(nt_tag)::value;
         for (int32_t c0 = 0; c0 < nt; c0 += chunk) {
             // the chunk's tiles c0 .. c0 + ct - 1: every array offset to its first tile
             const int32_t ct = chunk < nt - c0 ? chunk : nt - c0;
-            const size_t fo = (size_t)c0 * kTile;
-            float *r = w.r + fo * g.n, *s = w.s + fo * g.n, *eta = w.eta + fo * (size_t)g.E;
-            uint32_t *done = w.done + fo, *u[2] = {w.unsat[0] + fo, w.unsat[1] + fo};
-            int32_t *conv = w.conv + fo;
+            const Bufs b = chunk_bufs(w, g, c0);
+            k_ctrl_reset<<<1, 1, 0, stream>>>(w.ctrl);
+            size_t next_plan = 0;
             for (int32_t t = 1; t <= L; ++t) {
                 if (regular == 6 || regular == 7) {
                     auto *fn = regular == 6 ? (alpha ? k_check_dc<6, kRowsPerWave, NT, false>
@@ -540,28 +823,37 @@ int stream_decode(const ldpc_graph &g, const float *llr, int32_t B, int32_t L, u
                     const int32_t *cidx = g.stream_order.col_idx ? g.stream_order.col_idx : g.col_idx;
                     const int32_t *rcls = g.stream_order.row_class ? g.stream_order.row_class : g.row_class;
                     timed_launch(K_CHECK, fn, ct * row_blocks_dc, 64 * waves, 0, stream, cidx, rcls, g.m, g.n, g.E,
-                                 row_blocks_dc, r, s, eta, done, u[t & 1], t, alpha, beta, ncls);
+                                 row_blocks_dc, b, t, alpha, beta, ncls);
                 } else
                     timed_launch(K_CHECK, k_check<NT>, ct * row_blocks, 64 * waves, 0, stream, g.row_ptr, g.col_idx,
-                                 g.row_class, g.m, g.n, g.E, row_blocks, r, s, eta, done, u[t & 1], t, alpha, beta,
-                                 ncls);
+                                 g.row_class, g.m, g.n, g.E, row_blocks, b, t, alpha, beta, ncls);
                 // is the decision of iteration t - 1 tested?
                 const int32_t test_now = (period > 0 && (t - 1) % period == 0) ? 1 : 0;
                 timed_launch(K_BIT, k_bit<kColsPerWave, NT>, ct * col_blocks, 64 * waves, 0, stream, g.col_ptr,
                              (regular && g.stream_order.csc_edge) ? g.stream_order.csc_edge : g.csc_edge, g.n, g.E,
-                             col_blocks, r, s, eta, done, u[t & 1], u[(t + 1) & 1], conv, t, test_now);
+                             col_blocks, b, t, test_now);
+                while (next_plan < sizeof(kCompactAt) / sizeof(kCompactAt[0]) && kCompactAt[next_plan] < t) ++next_plan;
+                if (compact && t < L && next_plan < sizeof(kCompactAt) / sizeof(kCompactAt[0]) &&
+                    kCompactAt[next_plan] == t) {
+                    k_compact_plan<<<1, kPlanThreads, 0, stream>>>(b, ct, w.base);
+                    k_out_tiles<true><<<ct * nchunks, 256, 0, stream>>>(b, g.n, L, post, bits, iters, ok);
+                    k_compact_move<<<ct * move_blocks + (ct * kTile + 255) / 256, 256, 0, stream>>>(
+                        b, w.base, g.n, g.E, ct, move_blocks);
+                    k_compact_flip<<<1, 1, 0, stream>>>(w.ctrl);
+                }
             }
+            // the chunk's last decisions, then its outputs
+            const int32_t upar = (L + 1) & 1;
+            k_syndrome<<<ct * row_blocks, 64 * waves, 0, stream>>>(g.row_ptr, g.col_idx, g.m, g.n, row_blocks, b,
+                                                                   L == 0 ? 1 : 0, upar);
+            k_out_flags<<<(ct * kTile + 255) / 256, 256, 0, stream>>>(b, ct * kTile, L, upar, iters, ok);
+            k_out_tiles<false><<<ct * nchunks, 256, 0, stream>>>(b, g.n, L, post, bits, iters, ok);
         }
     };
     if (nt_msgs)
         iterate(std::true_type{});
     else
         iterate(std::false_type{});
-    uint32_t *unsat_final = w.unsat[(L + 1) & 1];
-    k_syndrome<<<nt * row_blocks, 64 * waves, 0, stream>>>(g.row_ptr, g.col_idx, g.m, g.n, row_blocks, L == 0 ? w.r : w.s,
-                                                    w.done, unsat_final);
-    k_finalize<<<(B + 255) / 256, 256, 0, stream>>>(B, L, w.conv, unsat_final, iters, ok);
-    k_from_tiles<<<nt * nchunks, 256, 0, stream>>>(w.r, w.s, w.conv, B, g.n, L, post, bits);
     return hipGetLastError() == hipSuccess ? LDPC_OK : LDPC_EHIP;
 }
 

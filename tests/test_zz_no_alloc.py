@@ -56,7 +56,7 @@ def test_noalloc_equals_workspace_decode(env, path):
     g = ldpc.build_graph(torch.from_numpy(H).to(dev))
     flags = ldpc.LDPC_FORCE_ONCHIP if path == "onchip" else ldpc.LDPC_FORCE_STREAM
     # first call larger than the second, so stale scratch contents would show
-    for B, eb, seed in ((700 if path == "stream" else 20000, 1.8, 31), (130, 2.2, 32)):
+    for B, eb, seed in ((340 if path == "stream" else 20000, 1.8, 31), (130, 2.2, 32)):
         note(f"[noalloc] path={path} B={B} Eb/N0={eb}")
         need = int(lib.ldpc_decode_workspace_bytes(g.handle, B, flags))
         assert need <= SCRATCH
@@ -72,7 +72,7 @@ def test_noalloc_refuses_oversized_workspace(env):
     torch, dev, ldpc, lib = env
     H = wl.regular_ldpc(1024, 512, 3, 6, seed=2)
     g = ldpc.build_graph(torch.from_numpy(H).to(dev))
-    B = 4096  # streaming path: 4096 frames need about 84 MB of workspace
+    B = 4096  # streaming path: 4096 frames need about 168 MB of workspace
     flags = ldpc.LDPC_FORCE_STREAM
     assert int(lib.ldpc_decode_workspace_bytes(g.handle, B, flags)) > SCRATCH
     llr = torch.zeros((B, 1024), dtype=torch.float32, device=dev)
