@@ -28,7 +28,10 @@
 //
 // Batches whose state exceeds the last-level (Infinity) cache are decoded in
 // chunks of whole tiles, all iterations of one chunk before the next, so that
-// every launch after a chunk's first finds its state in that cache.
+// every launch after a chunk's first finds its state in that cache.  Within a
+// chunk, the frames still decoding are packed into fewer tiles from time to
+// time (frame compaction, below), since a tile runs until its last frame
+// stops.
 #include <type_traits>
 
 #include "ldpc_internal.h"
