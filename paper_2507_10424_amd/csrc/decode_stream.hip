@@ -56,13 +56,13 @@ struct Set {
 };
 // Per chunk: which set holds its frames, and the last compaction plan.
 struct Ctrl {
-    uint32_t cur;   // set holding the chunk's frames
-    uint32_t go;    // the last plan compacts
+    uint32_t cur;   // set holding the chunk's frames at the last plan
+    uint32_t go;    // the last plan compacts: from its copy on, the frames are in set cur ^ 1
     int32_t active; // frames still decoding at the last plan
     uint32_t pad;
 };
 // What every streaming kernel of a chunk receives: both sets, offset to the
-// chunk's first tile, and its control words.  Kernels read ctrl->cur once.
+// chunk's first tile, and its control words.  Kernels read them once.
 struct Bufs {
     Set set[2];
     Ctrl *ctrl;
@@ -71,7 +71,15 @@ struct Bufs {
 // the kernel argument's array with a run-time value makes the compiler copy
 // the struct through LDS and turn its pointers into per-lane values.)
 __device__ __forceinline__ uint32_t *unsat_of(const Set &S, int32_t p) { return (p & 1) ? S.unsat[1] : S.unsat[0]; }
+// The set holding the chunk's frames outside a compaction (after the copy of
+// the last plan that went ahead).
 __device__ __forceinline__ Set cur_set(const Bufs &b) {
+    const uint32_t c = __builtin_amdgcn_readfirstlane(b.ctrl->cur ^ b.ctrl->go);
+    const Set s0 = b.set[0], s1 = b.set[1];
+    return c ? s1 : s0;
+}
+// The set the last plan counted (the source of its copy).
+__device__ __forceinline__ Set plan_set(const Bufs &b) {
     const uint32_t c = __builtin_amdgcn_readfirstlane(b.ctrl->cur);
     const Set s0 = b.set[0], s1 = b.set[1];
     return c ? s1 : s0;
@@ -533,41 +541,44 @@ __global__ void k_out_flags(const Bufs bufs, int32_t slots, int32_t L, int32_t u
 // iterations and convergence flags too; else, after the last iteration,
 // every frame still in a slot.
 template <bool STOPPED>
-__global__ __launch_bounds__(256) void k_out_tiles(const Bufs bufs, int32_t n, int32_t L, float *__restrict__ post,
-                                                   uint8_t *__restrict__ bits, int32_t *__restrict__ iters,
-                                                   uint8_t *__restrict__ ok) {
+__global__ __launch_bounds__(256) void k_out_tiles(const Bufs bufs, int32_t n, int32_t L, int32_t items,
+                                                   float *__restrict__ post, uint8_t *__restrict__ bits,
+                                                   int32_t *__restrict__ iters, uint8_t *__restrict__ ok) {
     if (STOPPED && !bufs.ctrl->go) return;
-    const Set S = cur_set(bufs);
+    const Set S = STOPPED ? plan_set(bufs) : cur_set(bufs);
     __shared__ float t[kTile][kTile + 1];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int32_t nchunks = (n + 63) / 64;
-    const int32_t tile = blockIdx.x / nchunks, j0 = (blockIdx.x % nchunks) * 64;
-    const int32_t f_lane = tile * kTile + lane;
-    const int32_t id_lane = S.fid[f_lane];
-    const bool emit = id_lane >= 0 && (!STOPPED || S.done[f_lane]);
-    if (!__syncthreads_or(emit)) return;
-    if (STOPPED && j0 == 0 && w == 0 && emit) { // a stopped frame: it stopped by the codeword test
-        iters[id_lane] = S.conv[f_lane];
-        if (ok) ok[id_lane] = 1;
-    }
-    const bool use_r = L == 0 || S.conv[f_lane] == 0;
-    const float *src = (use_r ? S.r : S.s) + (size_t)tile * n * kTile;
-#pragma unroll 4
-    for (int k = w; k < kTile; k += kWaves) {
-        const int32_t j = j0 + k;
-        t[lane][k] = (j < n) ? src[(size_t)j * kTile + lane] : 0.0f;
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int k = w; k < kTile; k += kWaves) {
-        const int32_t fk = tile * kTile + k;
-        const int64_t id = S.fid[fk];
-        const int32_t j = j0 + lane;
-        if (id >= 0 && (!STOPPED || S.done[fk]) && j < n) {
-            const float v = t[k][lane];
-            if (post) post[id * n + j] = v;
-            bits[id * n + j] = v < 0.0f ? 1 : 0;
+    for (int32_t item = blockIdx.x; item < items; item += gridDim.x) { // (tile, 64 bits)
+        const int32_t tile = item / nchunks, j0 = (item % nchunks) * 64;
+        const int32_t f_lane = tile * kTile + lane;
+        const int32_t id_lane = S.fid[f_lane];
+        const bool emit = id_lane >= 0 && (!STOPPED || S.done[f_lane]);
+        if (!__syncthreads_or(emit)) continue;
+        if (STOPPED && j0 == 0 && w == 0 && emit) { // a stopped frame: it stopped by the codeword test
+            iters[id_lane] = S.conv[f_lane];
+            if (ok) ok[id_lane] = 1;
         }
+        const bool use_r = L == 0 || S.conv[f_lane] == 0;
+        const float *src = (use_r ? S.r : S.s) + (size_t)tile * n * kTile;
+#pragma unroll 4
+        for (int k = w; k < kTile; k += kWaves) {
+            const int32_t j = j0 + k;
+            t[lane][k] = (j < n) ? src[(size_t)j * kTile + lane] : 0.0f;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int k = w; k < kTile; k += kWaves) {
+            const int32_t fk = tile * kTile + k;
+            const int64_t id = S.fid[fk];
+            const int32_t j = j0 + lane;
+            if (id >= 0 && (!STOPPED || S.done[fk]) && j < n) {
+                const float v = t[k][lane];
+                if (post) post[id * n + j] = v;
+                bits[id * n + j] = v < 0.0f ? 1 : 0;
+            }
+        }
+        __syncthreads(); // t is rewritten by the next item
     }
 }
 
@@ -614,21 +625,25 @@ __global__ __launch_bounds__(256) void k_from_tiles(const float *__restrict__ r,
 // ---- frame compaction ------------------------------------------------------
 // A 64-frame tile runs until its last frame stops.  Every so often (a fixed
 // schedule of iterations) one workgroup counts the frames still decoding in
-// the chunk; if packing them into fewer tiles frees at least a fifth of the
-// tiles that still run, the frames that have stopped are output, the others
+// the chunk; if packing them into fewer tiles saves enough tile-iterations
+// over the iterations left, the frames that have stopped are output, the others
 // are copied into the other set, packed (a tile's frames keep their order
 // and go to consecutive slots, so every store of a row is at most two
 // 256-byte pieces; the packed tiles are spread over the chunk so that every
 // XCD keeps some), the rest of that set's slots are marked empty, and the
-// chunk continues in that set.  Each frame's own
+// chunk continues in that set (the kernels take the set from the control
+// words: the set of the last plan, the other one if it went ahead).  Each
+// frame's own
 // arithmetic is unchanged: it sees the same launches in the same order.
 constexpr int kPlanThreads = 1024;
 constexpr int kMoveRows = 128; // rows of r, s and eta per wavefront of the copy
 
-__global__ __launch_bounds__(kPlanThreads) void k_compact_plan(const Bufs bufs, int32_t ct,
+__global__ __launch_bounds__(kPlanThreads) void k_compact_plan(const Bufs bufs, int32_t ct, int32_t remaining,
                                                                int32_t *__restrict__ base) {
     __shared__ int32_t part[kPlanThreads], tiles_on[kPlanThreads];
-    const Set S = cur_set(bufs);
+    // the frames are where the previous plan left them (copied if it went ahead)
+    const uint32_t c = __builtin_amdgcn_readfirstlane(bufs.ctrl->cur ^ bufs.ctrl->go);
+    const Set S = c ? bufs.set[1] : bufs.set[0];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = kPlanThreads / 64;
     for (int32_t tile = w; tile < ct; tile += nw) {
         const uint64_t on = __ballot(S.done[tile * kTile + lane] == 0u);
@@ -663,8 +678,14 @@ __global__ __launch_bounds__(kPlanThreads) void k_compact_plan(const Bufs bufs, 
     if (tid == 0) {
         const int32_t active = part[kPlanThreads - 1], t_on = tiles_on[kPlanThreads - 1];
         const int32_t packed = (active + kTile - 1) / kTile;
+        bufs.ctrl->cur = c;
         bufs.ctrl->active = active;
-        bufs.ctrl->go = (t_on - packed >= 1 && 5 * (t_on - packed) >= t_on) ? 1u : 0u;
+        // the copy reads the running tiles and writes the packed ones, about
+        // 0.4 of an iteration's bytes per tile for rate-1/2 codes: go when
+        // the tiles saved over the iterations left repay that twice
+        bufs.ctrl->go = (t_on - packed >= 1 && (int64_t)(t_on - packed) * remaining >= (int64_t)(t_on + packed))
+                            ? 1u
+                            : 0u;
     }
 }
 
@@ -681,70 +702,72 @@ __device__ __forceinline__ int32_t unspread(int32_t p, int32_t ct) {
     return p < 8 * stride ? (p % stride) * 8 + p / stride : p;
 }
 
-// Blocks 0 .. ct * blocks_per_tile - 1 copy the frames still decoding (one
-// source tile per blocks_per_tile blocks); the blocks after them mark the
-// destination slots past the packed frames empty.
+// Items 0 .. ct * blocks_per_tile - 1 copy the frames still decoding (one
+// source tile per blocks_per_tile items); the items after them mark the
+// destination slots past the packed frames empty.  A grid of at most a few
+// thousand workgroups walks the items, so a plan that does not go ahead
+// costs only that grid's launch.
 __global__ __launch_bounds__(256) void k_compact_move(const Bufs bufs, const int32_t *__restrict__ base, int32_t n,
-                                                      int64_t E, int32_t ct, int32_t blocks_per_tile) {
+                                                      int64_t E, int32_t ct, int32_t blocks_per_tile, int32_t items) {
     if (!bufs.ctrl->go) return;
     const uint32_t c = __builtin_amdgcn_readfirstlane(bufs.ctrl->cur);
     const Set src = c ? bufs.set[1] : bufs.set[0];
     const Set dst = c ? bufs.set[0] : bufs.set[1];
-    if ((int32_t)blockIdx.x >= ct * blocks_per_tile) {
-        const int32_t p = ((int32_t)blockIdx.x - ct * blocks_per_tile) * (int32_t)blockDim.x + threadIdx.x;
-        if (p >= ct * kTile) return;
-        if (unspread(p / kTile, ct) * kTile + p % kTile < bufs.ctrl->active) return;
-        dst.done[p] = 1u;
-        dst.unsat[0][p] = 0u;
-        dst.unsat[1][p] = 0u;
-        dst.conv[p] = -1;
-        dst.fid[p] = -1;
-        return;
-    }
-    const int32_t tile = blockIdx.x / blocks_per_tile, wb = blockIdx.x % blocks_per_tile;
     const int32_t w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int32_t f = tile * kTile + lane;
-    const bool act = src.done[f] == 0u;
-    const uint64_t on = __ballot(act);
-    if (on == 0ull) return;
-    const int32_t k = base[tile] + __popcll(on & ((1ull << lane) - 1ull)); // packed index
-    const int32_t dt = spread(k / kTile, ct), dl = k % kTile;
-    const int32_t ds = dt * kTile + dl; // destination slot
-    if (wb == 0 && w == 0 && act) {
-        dst.done[ds] = 0u;
-        dst.unsat[0][ds] = src.unsat[0][f];
-        dst.unsat[1][ds] = src.unsat[1][f];
-        dst.conv[ds] = src.conv[f];
-        dst.fid[ds] = src.fid[f];
-    }
-    // rows q of [r: n][s: n][eta: E] of this wavefront
-    const int64_t R = 2 * (int64_t)n + E;
-    const int64_t q0 = ((int64_t)wb * (blockDim.x >> 6) + w) * kMoveRows;
-    const int64_t q1 = q0 + kMoveRows < R ? q0 + kMoveRows : R;
-    auto copy = [&](const float *a, float *d, int64_t rows_per_tile, int64_t lo, int64_t hi) {
-        const float *ap = a + (size_t)tile * rows_per_tile * kTile + lane;
-        float *dp = d + (size_t)dt * rows_per_tile * kTile + dl;
-#pragma unroll 8
-        for (int64_t q = lo; q < hi; ++q) {
-            const float v = ap[(size_t)q * kTile];
-            if (act) dp[(size_t)q * kTile] = v;
+    const int32_t active = bufs.ctrl->active;
+    for (int32_t item = blockIdx.x; item < items; item += gridDim.x) {
+        if (item >= ct * blocks_per_tile) {
+            const int32_t p = (item - ct * blocks_per_tile) * (int32_t)blockDim.x + threadIdx.x;
+            if (p < ct * kTile && unspread(p / kTile, ct) * kTile + p % kTile >= active) {
+                dst.done[p] = 1u;
+                dst.unsat[0][p] = 0u;
+                dst.unsat[1][p] = 0u;
+                dst.conv[p] = -1;
+                dst.fid[p] = -1;
+            }
+            continue;
         }
-    };
-    if (q0 < n) copy(src.r, dst.r, n, q0, q1 < n ? q1 : n);
-    if (q1 > n && q0 < 2 * (int64_t)n)
-        copy(src.s, dst.s, n, (q0 > n ? q0 : n) - n, (q1 < 2 * (int64_t)n ? q1 : 2 * (int64_t)n) - n);
-    if (q1 > 2 * (int64_t)n) copy(src.eta, dst.eta, E, (q0 > 2 * (int64_t)n ? q0 : 2 * (int64_t)n) - 2 * n, q1 - 2 * n);
-}
-
-__global__ void k_compact_flip(Ctrl *ctrl) {
-    if (ctrl->go) ctrl->cur ^= 1u;
-    ctrl->go = 0u;
+        const int32_t tile = item / blocks_per_tile, wb = item % blocks_per_tile;
+        const int32_t f = tile * kTile + lane;
+        const bool act = src.done[f] == 0u;
+        const uint64_t on = __ballot(act);
+        if (on == 0ull) continue;
+        const int32_t k = base[tile] + __popcll(on & ((1ull << lane) - 1ull)); // packed index
+        const int32_t dt = spread(k / kTile, ct), dl = k % kTile;
+        const int32_t ds = dt * kTile + dl; // destination slot
+        if (wb == 0 && w == 0 && act) {
+            dst.done[ds] = 0u;
+            dst.unsat[0][ds] = src.unsat[0][f];
+            dst.unsat[1][ds] = src.unsat[1][f];
+            dst.conv[ds] = src.conv[f];
+            dst.fid[ds] = src.fid[f];
+        }
+        // rows q of [r: n][s: n][eta: E] of this wavefront
+        const int64_t R = 2 * (int64_t)n + E;
+        const int64_t q0 = ((int64_t)wb * (blockDim.x >> 6) + w) * kMoveRows;
+        const int64_t q1 = q0 + kMoveRows < R ? q0 + kMoveRows : R;
+        auto copy = [&](const float *a, float *d, int64_t rows_per_tile, int64_t lo, int64_t hi) {
+            const float *ap = a + (size_t)tile * rows_per_tile * kTile + lane;
+            float *dp = d + (size_t)dt * rows_per_tile * kTile + dl;
+#pragma unroll 8
+            for (int64_t q = lo; q < hi; ++q) {
+                const float v = ap[(size_t)q * kTile];
+                if (act) dp[(size_t)q * kTile] = v;
+            }
+        };
+        if (q0 < n) copy(src.r, dst.r, n, q0, q1 < n ? q1 : n);
+        if (q1 > n && q0 < 2 * (int64_t)n)
+            copy(src.s, dst.s, n, (q0 > n ? q0 : n) - n, (q1 < 2 * (int64_t)n ? q1 : 2 * (int64_t)n) - n);
+        if (q1 > 2 * (int64_t)n)
+            copy(src.eta, dst.eta, E, (q0 > 2 * (int64_t)n ? q0 : 2 * (int64_t)n) - 2 * n, q1 - 2 * n);
+    }
 }
 
 // Iterations after which a compaction is planned (roughly geometric: frames
 // stop early at high Eb/N0 and late at low).
-constexpr int32_t kCompactAt[] = {4, 6, 8, 11, 15, 20, 27, 35, 43};
+constexpr int32_t kCompactAt[] = {4, 6, 8, 11, 15, 20, 26, 32, 37, 42, 46};
+constexpr int32_t kCompactGrid = 2048; // workgroups of the output and copy kernels of a plan
 constexpr int32_t kCompactMinTiles = 16; // chunks of fewer tiles are not compacted
 
 } // namespace
@@ -838,11 +861,13 @@ int stream_decode(const ldpc_graph &g, const float *llr, int32_t B, int32_t L, u
                 while (next_plan < sizeof(kCompactAt) / sizeof(kCompactAt[0]) && kCompactAt[next_plan] < t) ++next_plan;
                 if (compact && t < L && next_plan < sizeof(kCompactAt) / sizeof(kCompactAt[0]) &&
                     kCompactAt[next_plan] == t) {
-                    k_compact_plan<<<1, kPlanThreads, 0, stream>>>(b, ct, w.base);
-                    k_out_tiles<true><<<ct * nchunks, 256, 0, stream>>>(b, g.n, L, post, bits, iters, ok);
-                    k_compact_move<<<ct * move_blocks + (ct * kTile + 255) / 256, 256, 0, stream>>>(
-                        b, w.base, g.n, g.E, ct, move_blocks);
-                    k_compact_flip<<<1, 1, 0, stream>>>(w.ctrl);
+                    const int32_t out_items = ct * nchunks;
+                    const int32_t move_items = ct * move_blocks + (ct * kTile + 255) / 256;
+                    k_compact_plan<<<1, kPlanThreads, 0, stream>>>(b, ct, L - t, w.base);
+                    k_out_tiles<true><<<out_items < kCompactGrid ? out_items : kCompactGrid, 256, 0, stream>>>(
+                        b, g.n, L, out_items, post, bits, iters, ok);
+                    k_compact_move<<<move_items < kCompactGrid ? move_items : kCompactGrid, 256, 0, stream>>>(
+                        b, w.base, g.n, g.E, ct, move_blocks, move_items);
                 }
             }
             // the chunk's last decisions, then its outputs
@@ -850,7 +875,7 @@ int stream_decode(const ldpc_graph &g, const float *llr, int32_t B, int32_t L, u
             k_syndrome<<<ct * row_blocks, 64 * waves, 0, stream>>>(g.row_ptr, g.col_idx, g.m, g.n, row_blocks, b,
                                                                    L == 0 ? 1 : 0, upar);
             k_out_flags<<<(ct * kTile + 255) / 256, 256, 0, stream>>>(b, ct * kTile, L, upar, iters, ok);
-            k_out_tiles<false><<<ct * nchunks, 256, 0, stream>>>(b, g.n, L, post, bits, iters, ok);
+            k_out_tiles<false><<<ct * nchunks, 256, 0, stream>>>(b, g.n, L, ct * nchunks, post, bits, iters, ok);
         }
     };
     if (nt_msgs)
