@@ -38,9 +38,9 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # 32-bit VALU lane-ops/s: 256 CUs x 64
 # reported as null.  Summaries: profiles/hbm_bytes_qc64800_regular1024.md.
 MEASURED_TRAFFIC = {
     ("regular1024", "onchip"): {"bytes": 609770803, "source": "onchip_kernel.h", "sha256_16": "3d2318242d8c9707"},
-    ("qc64800", "check"): {"bytes": 296865957, "source": "decode_stream.hip", "sha256_16": "cddb871934344f63",
+    ("qc64800", "check"): {"bytes": 296898742, "source": "decode_stream.hip", "sha256_16": "c2cbb7afe5374b91",
                            "tuning": {"path": 2, "stream_nt": -1, "stream_chunk": -1}},
-    ("qc64800", "bit"): {"bytes": 178183298, "source": "decode_stream.hip", "sha256_16": "cddb871934344f63",
+    ("qc64800", "bit"): {"bytes": 178185898, "source": "decode_stream.hip", "sha256_16": "c2cbb7afe5374b91",
                          "tuning": {"path": 2, "stream_nt": -1, "stream_chunk": -1}},
 }
 
