@@ -136,6 +136,8 @@ def parse():
     ap.add_argument("--no-c4", action="store_true", help="skip the n = 64800 block of the default line")
     ap.add_argument("--no-multi", action="store_true", help="skip the multi-code block of the default line")
     ap.add_argument("--no-c0", action="store_true", help="skip the n = 96 block of the default line")
+    ap.add_argument("--no-host-io", action="store_true",
+                    help="skip the decode from and to pinned host memory (PCIe-inclusive rate)")
     ap.add_argument("--profile-only", action="store_true", help="warmup + timed steps, no extras (for rocprofv3)")
     ap.add_argument("--multi-tuning", default=None,
                     help="multi8: per code variant,waves_per_simd,wg_per_cu of the on-chip path, codes separated "
@@ -444,6 +446,10 @@ def main():
         log(f"[bench] streaming path on the same workload: {stream_alt['coded_gbit_s']} Gbit/s, "
             f"HBM frac {stream_alt['hbm']['frac']}")
 
+    host_io = None
+    if args.config == "regular1024" and not args.no_host_io:
+        host_io = host_inclusive(args, g, llrs, outs, L, flags, side, side_ws, ws, n)
+
     nms = dense = None
     try:
         if not args.no_nms:
@@ -479,11 +485,65 @@ def main():
                    "tuning": tuning, "streams": nstreams},
         "edge_msg_per_s": edge_msgs, "info_gbit_s": round(gbits * k_info / n, 3) if k_info else None,
         "mean_iters": round(tot_iters / frames_step, 3), "per_point": per_point,
-        "roofline": roofline, "cpu_baseline": cpu, "hbm_resident_path": stream_alt, "whole_batch_stream": whole, "nms_vs_plain": nms,
+        "roofline": roofline, "cpu_baseline": cpu, "hbm_resident_path": stream_alt, "whole_batch_stream": whole,
+        "host_io": host_io, "nms_vs_plain": nms,
         "dense_ablation": dense, "qc64800": c4, "multi_code": multi, "regular96": c0,
         "paper_context": PAPER_CONTEXT,
     }
     print(json.dumps(line), flush=True)
+
+
+def host_inclusive(args, g, llrs, outs, L, flags, side, side_ws, ws, n):
+    """The timed step's decodes with the frames in pinned host memory: per
+    batch, the LLRs copied in, the decode, bits, posteriors, iterations and
+    flags copied out, batches spread over the step's streams so that copies
+    and decodes overlap.  `value` never includes this: the decoder's inputs
+    and outputs are device buffers; this is the rate a caller holding the
+    frames on the host would see over PCIe."""
+    import torch
+    from paper_2507_10424_amd import ldpc
+    dev = llrs[0].device
+    B = llrs[0].shape[0]
+    h_llr = [torch.empty(x.shape, dtype=x.dtype, pin_memory=True) for x in llrs]
+    for h, x in zip(h_llr, llrs):
+        h.copy_(x)
+    h_out = [tuple(torch.empty(t.shape, dtype=t.dtype, pin_memory=True) for t in o) for o in outs]
+    streams = side if side else [torch.cuda.current_stream()]
+    wss = side_ws if side else [ws]
+    k = len(streams)
+    d_llr = [torch.empty_like(llrs[0]) for _ in range(k)]
+    d_out = [ldpc._outputs(B, n, dev, True) for _ in range(k)]
+
+    def run():
+        cur = torch.cuda.current_stream()
+        for st in streams:
+            st.wait_stream(cur)
+        for i in range(len(llrs)):
+            j = i % k
+            with torch.cuda.stream(streams[j]):
+                d_llr[j].copy_(h_llr[i], non_blocking=True)
+                ldpc.minsum_decode(g, d_llr[j], L, flags=flags, workspace=wss[j], out=d_out[j])
+                for h, d in zip(h_out[i], d_out[j]):
+                    h.copy_(d, non_blocking=True)
+        for st in streams:
+            cur.wait_stream(st)
+
+    run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run()
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t0
+    same = all(torch.equal(h[0], o[0].cpu()) and torch.equal(h[2], o[2].cpu()) for h, o in zip(h_out, outs))
+    moved = sum(x.numel() * 4 for x in llrs) + sum(t.numel() * t.element_size() for o in outs for t in o)
+    res = {"coded_gbit_s": round(len(llrs) * B * n / sec / 1e9, 3), "ms_per_step": round(sec * 1e3, 3),
+           "pcie_bytes": moved, "pcie_gb_s": round(moved / sec / 1e9, 1), "streams": k,
+           "outputs_equal_device_step": bool(same),
+           "note": "LLRs from and bits, posteriors, iterations, flags to pinned host memory, host clock; "
+                   "copies and decodes of different batches overlap on the streams"}
+    log(f"[bench] from and to host memory: {res['coded_gbit_s']} Gbit/s ({res['pcie_gb_s']} GB/s over PCIe)")
+    del h_llr, h_out, d_llr, d_out
+    return res
 
 
 def host_cpu_info():
