@@ -68,6 +68,28 @@ def test_noalloc_equals_workspace_decode(env, path):
         assert want[2].min() >= 0 and want[2].max() <= 50
 
 
+def test_noalloc_stream_with_frame_compaction(env):
+    """The streaming path with frame compaction (chunks of at least 16 tiles):
+    the n = 96 code, 2,000 then 1,100 frames, both within the scratch array,
+    so the plans, copies and both state sets live in it."""
+    torch, dev, ldpc, lib = env
+    H = wl.regular_ldpc(96, 48, 3, 6, seed=1)
+    g = ldpc.build_graph(torch.from_numpy(H).to(dev))
+    flags = ldpc.LDPC_FORCE_STREAM
+    for B, eb, seed in ((2000, 2.0, 41), (1100, 2.5, 42)):
+        note(f"[noalloc] path=stream n=96 B={B} Eb/N0={eb}")
+        assert (B + 63) // 64 >= 16  # chunks of 16 tiles or more are compacted
+        need = int(lib.ldpc_decode_workspace_bytes(g.handle, B, flags))
+        assert need <= SCRATCH
+        llr = torch.from_numpy(wl.bpsk_awgn_llr(None, eb, 0.5, seed=seed, n=96, batch=B)).to(dev)
+        want = _run(torch, dev, ldpc, lib, g, llr, 50, flags, noalloc=False)
+        got = _run(torch, dev, ldpc, lib, g, llr, 50, flags, noalloc=True)
+        for a, b, name in zip(got, want, ("bits", "post", "iters", "ok")):
+            assert np.array_equal(a, b), (B, name)
+        # frames stop at different iterations, so the plans have frames to pack
+        assert want[2].min() < 10 and want[2].max() > 20
+
+
 def test_noalloc_refuses_oversized_workspace(env):
     torch, dev, ldpc, lib = env
     H = wl.regular_ldpc(1024, 512, 3, 6, seed=2)
