@@ -117,7 +117,10 @@ size_t ldpc_decode_workspace_bytes(const ldpc_graph *g, int32_t B, uint32_t flag
 /*
  * Min-Sum decoding of B frames (Algorithm 1, with the pre-loop codeword test
  * of the paper's kernel listing, Sec. IV).
- *   llr_dev   B x n float32 channel LLRs.
+ *   llr_dev   B x n float32 channel LLRs, finite.  A frame holding an
+ *             infinite or NaN LLR gets unspecified outputs (bits still 0/1,
+ *             iterations still within 0..L); the other frames' outputs and
+ *             the status are unaffected, and no access leaves the buffers.
  *   B         frames, B >= 0 (B == 0 is a no-op).
  *   max_iter  L >= 0 iterations at most.
  *   flags     LDPC_* decode flags.

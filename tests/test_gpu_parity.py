@@ -134,6 +134,31 @@ def test_adversarial_llrs(path):
 
 
 @pytest.mark.parametrize("path", sorted(PATHS))
+def test_non_finite_llrs_stay_in_their_frame(path):
+    """Infinite and NaN LLRs (outside the contract: their frames' outputs are
+    unspecified) leave every other frame equal to the oracle, and the outputs
+    of their own frames within their ranges."""
+    H = wl.regular_ldpc(96, 48, 3, 6, seed=1)
+    L = 20
+    llr = wl.bpsk_awgn_llr(None, 2.0, 0.5, seed=51, n=96, batch=256).astype(np.float32)
+    bad = np.arange(40, 72)
+    rng = np.random.default_rng(52)
+    for k, f in enumerate(bad):
+        if k % 4 == 0:
+            llr[f, :] = np.nan
+        else:
+            cols = rng.choice(96, size=1 + k % 5, replace=False)
+            llr[f, cols] = [np.inf, -np.inf, np.nan][k % 3]
+    note(f"[parity] non-finite LLRs path={path} frames={bad.size} of {llr.shape[0]}")
+    gb, gp, gi, go = gpu_decode(H, llr, L, PATHS[path])
+    good = np.setdiff1d(np.arange(llr.shape[0]), bad)
+    ref = oracle_decode(H, llr[good], L, PATHS[path])
+    assert_parity((gb[good], gp[good], gi[good], go[good]), ref, "finite frames beside non-finite ones")
+    assert np.isin(gb[bad], (0, 1)).all() and np.isin(go[bad], (0, 1)).all()
+    assert (gi[bad] >= 0).all() and (gi[bad] <= L).all()
+
+
+@pytest.mark.parametrize("path", sorted(PATHS))
 def test_nms_weights(path):
     H = wl.random_irregular_code(120, 60, seed=4, dv_choices=(2, 3, 4))
     import oracle
