@@ -354,6 +354,29 @@ def main():
                     "kernel": dom,
                     "kernel_ms_per_launch": round(dom_ms / dom_launches, 4), "launches_per_step": dom_launches}
 
+    # the same fraction per Eb/N0 point (one more decode of each batch, alone
+    # on one stream): the per-frame cost of a refill weighs more where frames
+    # stop after a few iterations
+    for p, (x, o) in enumerate(zip(llrs, outs)):
+        lib.ldpc_timing_enable(1)
+        ldpc.minsum_decode(g, x, L, flags=flags, workspace=ws, out=o)
+        torch.cuda.synchronize()
+        kt = {}
+        for kid, kname in [(0, "check"), (1, "bit"), (2, "onchip")]:
+            ms_k, cnt = ctypes.c_double(), ctypes.c_int64()
+            lib.ldpc_timing_read(kid, ctypes.byref(ms_k), ctypes.byref(cnt))
+            kt[kname] = ms_k.value
+        lib.ldpc_timing_enable(0)
+        pits = o[2].to(torch.float64)
+        if dom == "onchip":
+            fr = alu_ops_per_frame_iter(H) * float(pits.sum()) / (kt["onchip"] * 1e-3) / 1e12 / VALU_PEAK_TOPS
+            per_point[p]["kernel_ms"] = round(kt["onchip"], 4)
+        else:
+            pb = float((pits * (12 * E + 12 * n)).sum() - (pits >= 1).double().sum() * 4 * E)
+            fr = pb / ((kt["check"] + kt["bit"]) * 1e-3) / 1e9 / HBM_PEAK_GBS
+            per_point[p]["kernel_ms"] = round(kt["check"] + kt["bit"], 4)
+        per_point[p]["roofline_frac"] = round(fr, 4)
+
     cpu = None
     if not args.no_cpu_baseline:
         # the oracle on the same frames: the first `per` frames of every Eb/N0
