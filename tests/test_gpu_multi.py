@@ -191,3 +191,34 @@ def test_qc_family_configured_batches_one_call(tdev):
         got = tuple(t.cpu().numpy()[pick] for t in o)
         note(f"[multi] code {k}: n={H.shape[1]} B={B}, {pick.size} frames checked, mean iters {got[2].mean():.2f}")
         assert_parity(got, oracle_decode(H, llr[pick], 50), f"configured batch, code {k}")
+
+
+def test_sixteen_jobs_and_one_more(tdev):
+    """The most jobs one call takes (16): the eight QC codes at small batches,
+    then eight (3,6) codes (four graphs, each twice, some large enough for a
+    launch of their own), every frame against the oracle; a 17th job is
+    refused before anything runs."""
+    torch, dev = tdev
+    from paper_2507_10424_amd import ldpc
+    specs = [(c["H"], c["rate"], 40 + 25 * k) for k, c in enumerate(wl.qc_multi_code_family(seed=7))]
+    regs = [wl.regular_ldpc(96, 48, 3, 6, seed=1), wl.regular_ldpc(1024, 512, 3, 6, seed=2),
+            wl.regular_ldpc(192, 96, 3, 6, seed=3), wl.regular_ldpc(480, 240, 3, 6, seed=4)]
+    specs += [(regs[k % 4], 0.5, B) for k, B in enumerate((300, 4000, 120, 257, 64, 3000, 1, 500))]
+    graphs = {}
+    jobs, inputs = [], []
+    for k, (H, rate, B) in enumerate(specs):
+        key = id(H)
+        if key not in graphs:
+            graphs[key] = ldpc.build_graph(torch.from_numpy(H).to(dev))
+        llr = wl.bpsk_awgn_llr(None, 2.0, rate, seed=600 + k, n=H.shape[1], batch=B)
+        jobs.append((graphs[key], torch.from_numpy(llr).to(dev)))
+        inputs.append((H, llr))
+    assert len(jobs) == 16
+    note(f"[multi] 16 jobs, batches {[s[2] for s in specs]}")
+    outs = ldpc.minsum_decode_multi(jobs, 30)
+    torch.cuda.synchronize()
+    for k, ((H, llr), o) in enumerate(zip(inputs, outs)):
+        assert_parity(tuple(t.cpu().numpy() for t in o), oracle_decode(H, llr, 30), f"16 jobs, job {k}")
+    with pytest.raises(ldpc.LdpcError) as e:
+        ldpc.minsum_decode_multi(jobs + [jobs[0]], 30)
+    assert e.value.name == "LDPC_EUNSUPPORTED"
