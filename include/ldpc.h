@@ -374,8 +374,11 @@ int ldpc_graph_get_tuning(const ldpc_graph *g, ldpc_tuning *t);
  * Autotuner: generates B all-zero frames at ebn0_db on the device, times one
  * warm-up and three decodes (at most max_iter iterations, early exit) for
  * every launch choice that applies to the graph (each fitting on-chip
- * variant, both register budgets, 0..4 workgroups per CU, leaving out
- * kernels that spill registers unless nothing else fits; the streaming path
+ * variant under three register budgets, the compiler's and at least 4 or 3
+ * waves per SIMD, a tighter one only where the compiler's kernel takes more
+ * than 128 or 168 registers, 0..4 workgroups per CU, leaving out kernels
+ * that spill under the compiler's budget unless nothing else fits and those
+ * that spill more than 320 bytes under a tighter one; the streaming path
  * with 1, 2, 4, 8 wavefronts per workgroup, with and without non-temporal
  * message accesses, whole batch and chunks by size where those differ), times the four fastest again (three interleaved rounds
  * of four decodes), and stores the fastest of those in the graph's tuning
