@@ -1,6 +1,11 @@
-"""Seeded random sweep (GPU): code shapes, batch sizes, iteration limits,
-flags (no early exit, codeword-test period), kernel paths and learned
-weights, every case against the CPU oracle."""
+"""Seeded random sweep (GPU): code shapes, batch sizes (up to the sizes the
+streaming decoder compacts), iteration limits, flags (no early exit,
+codeword-test period), kernel paths, launch choices (on-chip variant,
+register budget and workgroups per CU; streaming wavefronts, non-temporal
+messages and chunks) and learned weights, every case against the CPU oracle.
+LDPC_RANDOM_CASES sets the number of cases (48 by default)."""
+import os
+
 import numpy as np
 import pytest
 
@@ -9,7 +14,7 @@ from parity import assert_parity, note, oracle_decode
 
 pytestmark = pytest.mark.gpu
 
-N_CASES = 48
+N_CASES = int(os.environ.get("LDPC_RANDOM_CASES", "48"))
 
 
 def _case(k):
@@ -52,10 +57,29 @@ def test_random_case(k):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     kind, H, B, L, flags, path, learned, llr, rng = _case(k)
-    note(f"[random {k}] {kind} m={H.shape[0]} n={H.shape[1]} B={B} L={L} flags={flags} path={path} "
-         f"learned={learned}")
     dev = torch.device("cuda:0")
     g = ldpc.build_graph(torch.from_numpy(H).to(dev))
+    rs = np.random.default_rng(777 + k)
+    if rs.random() < 0.35:  # large enough for frame compaction on the streaming path
+        B = int(rs.choice([1024, 1100, 1500, 2049]))
+        llr = (rs.normal(1.0, rs.uniform(0.6, 2.0), size=(B, H.shape[1])) * rs.uniform(0.5, 4.0)).astype(np.float32)
+    tun = None
+    if path == 2 or (path == 0 and rs.random() < 0.5):
+        tun = dict(path=2, stream_waves=int(rs.choice([1, 2, 4, 8])), stream_nt=int(rs.choice([-1, 0, 1])),
+                   stream_chunk=int(rs.choice([-1, 0, 1, 2, 16])))
+        ldpc.set_tuning(g, **tun)
+    elif path in (0, 4):
+        for _ in range(20):  # a variant that fits the graph, if one of 20 draws does
+            cand = dict(path=1, variant=int(rs.integers(0, 42)), wg_per_cu=int(rs.integers(0, 5)),
+                        waves_per_simd=int(rs.choice([0, 4, 3])))
+            try:
+                ldpc.set_tuning(g, **cand)
+                tun = cand
+                break
+            except ldpc.LdpcError:
+                continue
+    note(f"[random {k}] {kind} m={H.shape[0]} n={H.shape[1]} B={B} L={L} flags={flags} path={path} "
+         f"learned={learned} tuning={tun}")
     x = torch.from_numpy(llr).to(dev)
     try:
         if learned:
