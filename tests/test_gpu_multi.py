@@ -222,3 +222,48 @@ def test_sixteen_jobs_and_one_more(tdev):
     with pytest.raises(ldpc.LdpcError) as e:
         ldpc.minsum_decode_multi(jobs + [jobs[0]], 30)
     assert e.value.name == "LDPC_EUNSUPPORTED"
+
+
+N_RANDOM_CALLS = int(__import__("os").environ.get("LDPC_RANDOM_MULTI", "6"))
+
+
+@pytest.mark.parametrize("k", range(N_RANDOM_CALLS))
+def test_random_job_lists(tdev, k):
+    """Seeded random calls: 1 to 16 jobs drawn from thirteen codes (a code may
+    appear in several jobs), batches of 0 to 700 frames, launch choices set on
+    some graphs, random L and flags; every job against the oracle.
+    LDPC_RANDOM_MULTI sets the number of calls (6 by default)."""
+    torch, dev = tdev
+    from paper_2507_10424_amd import ldpc
+    pool = [c["H"] for c in wl.qc_multi_code_family(seed=7)] + [
+        wl.regular_ldpc(96, 48, 3, 6, seed=1), wl.regular_ldpc(1024, 512, 3, 6, seed=2),
+        wl.regular_ldpc(240, 120, 3, 6, seed=5),
+        wl.random_irregular_code(300, 120, seed=3, dv_choices=(1, 2, 3, 4), max_row_degree=8),
+        wl.random_irregular_code(200, 90, seed=9, dv_choices=(2, 3, 6), max_row_degree=16)]
+    rs = np.random.default_rng(5000 + k)
+    idx = rs.integers(0, len(pool), size=int(rs.integers(1, 17)))
+    L = int(rs.integers(0, 40))
+    flags = int(rs.choice([0, 1, 2 << 8, 3 << 8]))
+    graphs, jobs, inputs = {}, [], []
+    for h in idx:
+        H = pool[h]
+        if h not in graphs:
+            graphs[h] = ldpc.build_graph(torch.from_numpy(H).to(dev))
+            if rs.random() < 0.3:
+                for _ in range(10):  # a variant that fits, if one of 10 draws does
+                    try:
+                        ldpc.set_tuning(graphs[h], 1, variant=int(rs.integers(0, 42)),
+                                        wg_per_cu=int(rs.integers(0, 5)), waves_per_simd=int(rs.choice([0, 4, 3])))
+                        break
+                    except ldpc.LdpcError:
+                        continue
+        B = int(rs.choice([0, 1, 7, 64, 200, 700]))
+        llr = (rs.normal(1.0, rs.uniform(0.6, 1.6), size=(B, H.shape[1])) * rs.uniform(0.5, 3.0)).astype(np.float32)
+        jobs.append((graphs[h], torch.from_numpy(llr).to(dev)))
+        inputs.append((H, llr))
+    note(f"[multi random {k}] codes {idx.tolist()} batches {[x.shape[0] for _, x in inputs]} L={L} flags={flags}")
+    outs = ldpc.minsum_decode_multi(jobs, L, flags=flags)
+    torch.cuda.synchronize()
+    for j, ((H, llr), o) in enumerate(zip(inputs, outs)):
+        if llr.shape[0]:
+            assert_parity(tuple(t.cpu().numpy() for t in o), oracle_decode(H, llr, L, flags), f"random {k} job {j}")
