@@ -242,3 +242,61 @@ def test_gradient_with_state_in_device_memory(tdev):
     ref = oracle.nms_train_grad_f32_forward(H, llr, a, b, llr_grad=False)
     assert abs(float(loss) - ref["loss"]) <= 2e-5 * abs(ref["loss"])
     assert_grad_parity(H, T, B, {"galpha": ga.cpu().numpy(), "gbeta": gb.cpu().numpy()}, ref, "qc6480")
+
+
+N_RANDOM_GRAD = int(__import__("os").environ.get("LDPC_RANDOM_GRAD", "8"))
+
+
+@pytest.mark.parametrize("k", range(N_RANDOM_GRAD))
+def test_random_gradient_cases(tdev, k):
+    """Seeded random codes (regular, irregular, QC), T = 1..12, checkpoint
+    intervals 1, 2, 3 or T, 1..40 frames, random weights and Eb/N0: forward
+    posteriors, loss and every gradient entry against the oracle's reverse
+    sweep along the binary32 decisions.  LDPC_RANDOM_GRAD sets the number of
+    cases (8 by default)."""
+    torch, dev = tdev
+    from paper_2507_10424_amd import ldpc
+    rs = np.random.default_rng(9000 + k)
+    kind = rs.choice(["regular", "irregular", "qc"])
+    if kind == "regular":
+        dv, dc = [(3, 6), (2, 4), (4, 8)][rs.integers(3)]
+        m = int(rs.integers(4, 40)) * dv
+        H = wl.regular_ldpc(m * dc // dv, m, dv, dc, seed=int(rs.integers(1 << 30)))
+    elif kind == "irregular":
+        n = int(rs.integers(20, 400))
+        m = int(rs.integers(n // 6 + 2, n // 2 + 3))
+        H = None
+        for cap in (12, 16, 40):
+            try:
+                H = wl.random_irregular_code(n, m, seed=int(rs.integers(1 << 30)), dv_choices=(1, 2, 3, 4, 6),
+                                             max_row_degree=cap)
+                break
+            except RuntimeError:
+                continue
+        if H is None:
+            pytest.skip("no code of this shape")
+    else:
+        Z = int(rs.choice([8, 16, 24]))
+        H = wl.qc_irregular_ldpc(12, 6, Z, [2] * 6 + [3] * 4 + [6] * 2, seed=int(rs.integers(1 << 30)))
+    C = oracle.check_degrees(H).size
+    if C > 8:
+        pytest.skip("more than 8 degree classes (the training kernels' limit)")
+    T = int(rs.integers(1, 13))
+    K = int(rs.choice([1, 2, 3, T]))
+    B = int(rs.integers(1, 41))
+    a = rs.uniform(0.5, 1.1, size=(T, C)).astype(np.float32)
+    b = rs.uniform(0.0, 0.4, size=(T, C)).astype(np.float32)
+    llr = wl.bpsk_awgn_llr(None, float(rs.uniform(0.5, 3.5)), max(0.1, 1 - H.shape[0] / H.shape[1]),
+                           seed=int(rs.integers(1 << 30)), n=H.shape[1], batch=B)
+    note(f"[nms-grad random {k}] {kind} m={H.shape[0]} n={H.shape[1]} T={T} K={K} B={B}")
+    g = _graph(torch, dev, H)
+    at, bt, lt = (torch.from_numpy(x).to(dev) for x in (a, b, llr))
+    ws = torch.empty(ldpc.train_workspace_bytes(g, B, T, K), dtype=torch.uint8, device=dev)
+    loss, post = ldpc.nms_train_forward(g, lt, at, bt, K, ws, want_post=True)
+    ga, gb, gl = ldpc.nms_train_backward(g, lt, at, bt, K, ws, want_llr_grad=True)
+    torch.cuda.synchronize()
+    ref = oracle.nms_train_grad_f32_forward(H, llr, a, b, llr_grad=True)
+    assert np.array_equal(post.cpu().numpy().astype(np.float64), ref["post"])
+    assert abs(float(loss) - ref["loss"]) <= 2e-5 * abs(ref["loss"])
+    assert_grad_parity(H, T, B, {"galpha": ga.cpu().numpy(), "gbeta": gb.cpu().numpy(), "gllr": gl.cpu().numpy()},
+                       ref, f"random {k}")
