@@ -19,12 +19,12 @@ def tdev():
 
 @pytest.mark.parametrize("flags", [0, 2])  # auto (on-chip) and forced streaming
 @pytest.mark.parametrize("n", [96, 1024])
-def test_replays_match_eager(tdev, flags, n):
+@pytest.mark.parametrize("B", [700, 1500])  # streaming: 1,500 frames (24 tiles) are compacted
+def test_replays_match_eager(tdev, flags, n, B):
     torch, dev = tdev
     from paper_2507_10424_amd import ldpc
     H = wl.regular_ldpc(n, n // 2, 3, 6, seed=1 if n == 96 else 2)
     g = ldpc.build_graph(torch.from_numpy(H).to(dev))
-    B = 700
     cap = ldpc.CapturedDecode(g, B, 30, flags=flags)
     for rep in range(4):
         x = wl.bpsk_awgn_llr_torch(None, 1.0 + 0.5 * rep, 0.5, 900 + rep, dev, n=n, batch=B)
@@ -34,7 +34,7 @@ def test_replays_match_eager(tdev, flags, n):
         want = ldpc.minsum_decode(g, x.clone(), 30, flags=flags)
         torch.cuda.synchronize()
         for a, b in zip(got, want):
-            assert torch.equal(a, b), (rep, flags, n)
+            assert torch.equal(a, b), (rep, flags, n, B)
 
 
 def test_multi_code_replays(tdev):
