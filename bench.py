@@ -116,7 +116,7 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="regular1024", choices=["regular1024", "qc64800", "regular96", "multi8"])
     ap.add_argument("--no-autotune", action="store_true", help="skip the autotuner (library defaults)")
     ap.add_argument("--tuning", default=None,
