@@ -72,8 +72,8 @@ def test_qc64800_full_batch(dev, ebn0):
     llr = wl.bpsk_awgn_llr_torch(None, ebn0, 0.5, 500, dev, n=H.shape[1], batch=4096)
     gb, gp, gi, go = _decode_full(H, llr, 50, 1.2)
     _check_all_frames(H, (gb, gp, gi, go), 50)
-    idx = _sample(gi, 4, np.random.default_rng(1))
-    note(f"[large] n=64800 at {ebn0} dB, checking frames {idx.tolist()}, mean iters {gi.mean():.2f}")
+    idx = _sample(gi, 48, np.random.default_rng(1))
+    note(f"[large] n=64800 at {ebn0} dB, checking {idx.size} frames, mean iters {gi.mean():.2f}")
     ref = oracle_decode(H, llr.cpu().numpy()[idx], 50)
     assert_parity((gb[idx], gp[idx], gi[idx], go[idx]), ref, f"n=64800 {ebn0} dB sampled")
 
@@ -99,8 +99,8 @@ def test_qc64800_learned_full_batch(dev):
     torch.cuda.synchronize()
     gb, gp, gi, go = (t.cpu().numpy() for t in out)
     _check_all_frames(H, (gb, gp, gi, go), T)
-    idx = _sample(gi, 3, np.random.default_rng(2))
-    note(f"[large] learned n=64800, checking frames {idx.tolist()}, mean iters {gi.mean():.2f}")
+    idx = _sample(gi, 24, np.random.default_rng(2))
+    note(f"[large] learned n=64800, checking {idx.size} frames, mean iters {gi.mean():.2f}")
     ref = oracle_decode(H, llr.cpu().numpy()[idx], T, 0, alpha, beta)
     assert_parity((gb[idx], gp[idx], gi[idx], go[idx]), ref, "learned n=64800 sampled")
 
